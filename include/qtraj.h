@@ -1,0 +1,223 @@
+/*
+ * qtraj.h -- C ABI of the MI355X quantum-trajectory solver.
+ *
+ * The library evolves many independent radial wave functions u_l(r) of a
+ * heavy quark-antiquark pair with the waiting-time Monte-Carlo wave-function
+ * method of QTraj 1.0 (Ba Omar et al., arXiv:2107.06147):
+ *   - split-step (Strang) pseudo-spectral steps under the non-Hermitian
+ *     effective Hamiltonian of the Munich potential (paper: Sec. "Algorithm
+ *     for deterministic evolution between quantum jumps", eq. (uUpdate), and
+ *     the appendix "Munich potential");
+ *   - after each step the norm (eq. (normcond)) is compared with the
+ *     trajectory's random threshold; when it has dropped to the threshold a
+ *     quantum jump l -> l +- 1, singlet <-> octet is applied with the
+ *     probabilities of eqs. (Pl+-) and (pjump) and the state is multiplied by
+ *     r and renormalised (Secs. "The waiting time approach" and "Summary of
+ *     QTraj execution").
+ *
+ * Conventions (natural units: GeV, GeV^-1).
+ *   grid     dr = L/N, r_j = j dr, j = 1..N-1, u(0) = u(L) = 0.  A wave
+ *            function is N complex values indexed by j; element 0 is 0.
+ *   kinetic  p_k = pi k / L; E_k = p_k^2 / M (deriv_type 0) or
+ *            2 (1 - cos(p_k dr)) / (M dr^2) (deriv_type 1), M the heavy-quark
+ *            mass (reduced mass M/2).
+ *   potential alpha = (4/3) alpha_s, kappa = kappa_hat T^3, gamma = gamma_hat T^3
+ *            singlet V = -alpha/r + gamma r^2/2  - i kappa r^2/2
+ *            octet   V = +alpha/(8r) + 7 gamma r^2/32 - i 7 kappa r^2/32
+ *            plus l(l+1)/(M r^2).
+ *   time     t_n = tau_start + n dt; step n uses T(t_n), linear in the table.
+ *   steps    a trajectory takes n_steps = min(max_steps, first n with
+ *            t_n > tau[last] or T(t_n) < T_final) steps.
+ *   random   Philox4x64-10, key (seed, 0), counter (event+1, trajectory id,
+ *            0, 0); event 0 gives the first threshold (word 2), event e >= 1
+ *            (the e-th jump) gives u_l (word 0), u_c (word 1) and the next
+ *            threshold (word 2); u = ((w >> 12) + 0.5) 2^-52.
+ *   jump     iff norm <= threshold; l -> l-1 iff u_l < l/(2l+1), else l+1;
+ *            octet -> singlet iff u_c < 2/7, singlet -> octet always.
+ *   results  overlaps with the six Coulomb states 1S,2S,1P,3S,2P,1D (Bohr
+ *            radius 2/(M alpha), normalised on the grid) of the final
+ *            normalised state, non-zero only for a singlet of matching l;
+ *            survival = overlap / initial overlap (raw overlap where the
+ *            initial overlap is 0).
+ *
+ * Threading: a context may be used from one host thread at a time; distinct
+ * contexts are independent.  A server (qt_server_*) is thread-safe.
+ * Errors: every call returns a qt_status; no call aborts.  qt_last_error()
+ * gives a message for the calling thread's last failure.
+ */
+#ifndef QTRAJ_H
+#define QTRAJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QT_OK = 0,
+    QT_EINVAL = 1,      /* an argument failed validation; nothing was run     */
+    QT_ENOMEM = 2,      /* device or host allocation failed / over budget     */
+    QT_EDEVICE = 3,     /* a HIP runtime call failed                          */
+    QT_EBUSY = 4,       /* resource in use                                    */
+    QT_ETIMEOUT = 5,    /* qt_wait ran out of time                            */
+    QT_ECANCELED = 6,   /* the request was cancelled                          */
+    QT_ENOTFOUND = 7    /* unknown request id                                 */
+} qt_status;
+
+typedef enum { QT_FP64 = 0, QT_FP32_BULK = 1 } qt_precision;
+/* FUSED: one persistent kernel, state in registers/LDS for the whole run.
+ * PLAIN: one kernel per sub-step per time step, state in HBM (FP64 only). */
+typedef enum { QT_FORM_FUSED = 0, QT_FORM_PLAIN = 1 } qt_form;
+typedef enum { QT_INIT_COULOMB = 0, QT_INIT_GAUSSIAN = 1, QT_INIT_ARRAY = 2 } qt_init_kind;
+typedef enum { QT_SINGLET = 0, QT_OCTET = 1 } qt_color;
+/* LMAX: l exceeded the tabulated range (l > 255; ends like MAXJUMPS). */
+typedef enum { QT_TRAJ_OK = 0, QT_TRAJ_RMAX = 1, QT_TRAJ_MAXJUMPS = 2, QT_TRAJ_LMAX = 3 } qt_traj_status;
+enum { QT_FLAG_KINETIC_OFF = 1 };   /* kinetic factor := 1 (test special case) */
+
+/* Physics and grid (paper: table "Code parameters", groups Physics, Jump,
+ * Grid).  Valid: N a power of two in [256, 8192]; L, dt, mass > 0;
+ * alpha_s >= 0; kappa_hat >= 0; gamma_hat <= 0; deriv_type 0 or 1;
+ * 0 < r_max <= 1; max_jumps < 0 means unlimited. */
+typedef struct {
+    int32_t N;
+    double  L, dt, mass, alpha_s, kappa_hat, gamma_hat;
+    int32_t deriv_type, do_jumps, max_jumps;
+    double  r_max;
+    int32_t flags;
+} qt_physics;
+
+/* Temperature table (paper: Temperature parameters).  Host pointers, read
+ * during the call.  tau in GeV^-1 strictly increasing, n >= 2. */
+typedef struct {
+    const double* tau;
+    const double* T;
+    int32_t n;
+    double  tau_start, T_final;
+    int64_t max_steps;
+} qt_ttable;
+
+/* Initial state (paper: Initial condition parameters).  COULOMB: hydrogen-
+ * like (n, l) for n <= 3; GAUSSIAN: r^{l+1} exp(-r^2/(2 width^2)); ARRAY:
+ * u_re/u_im host arrays of N values indexed by j (u_im may be NULL).  Every
+ * initial state is normalised on the grid. */
+typedef struct {
+    int32_t kind, n, l, color;
+    double  width;
+    const double* u_re;
+    const double* u_im;
+} qt_init;
+
+/* Trajectory i of a batch has id traj_id0 + i * traj_id_stride (stride 0 is
+ * read as 1); ids select the random streams, so results do not depend on
+ * how trajectories are batched.  precision: qt_precision; form: qt_form. */
+typedef struct {
+    int64_t  n_traj;
+    uint64_t seed, traj_id0, traj_id_stride;
+    int32_t  precision, form;
+} qt_batch;
+
+/* Per-trajectory outputs, DEVICE pointers owned by the caller.  Any pointer
+ * may be NULL.  overlap/survival hold 6 values per trajectory; psi holds N
+ * complex doubles (re, im interleaved) per trajectory; min_gap is the
+ * smallest |norm - threshold| over all jump decisions (diagnostic for
+ * comparisons near the threshold). */
+typedef struct {
+    double  *norm, *first_r, *overlap, *survival, *mean_r;
+    int32_t *l, *color, *n_jumps, *status;
+    int64_t *steps_done;
+    double  *min_gap;
+    double  *psi;
+} qt_results;
+
+typedef struct qt_context qt_context;
+typedef struct qt_job qt_job;
+typedef struct qt_server qt_server;
+
+/* Creates a context on HIP device `device` (ordinal).  QT_EDEVICE if the
+ * device does not exist. */
+qt_status qt_context_create(int device, qt_context** out);
+qt_status qt_context_destroy(qt_context* ctx);
+
+/* Runs one batch to completion, stream-ordered on `hip_stream` (a
+ * hipStream_t; NULL = default stream): validates, builds the tables on the
+ * host, uploads them and launches the kernels.  Results are valid once the
+ * stream reaches this point.  Host inputs may be freed when the call
+ * returns. */
+qt_status qt_run(qt_context* ctx, const qt_physics* phys, const qt_ttable* tt,
+                 const qt_init* init, const qt_batch* batch, const qt_results* dev_out,
+                 void* hip_stream);
+
+/* Several batches of possibly different N and lifetimes in one job: every
+ * batch keeps its own physics, table and initial state; trajectories are
+ * scheduled longest-first on persistent workgroups that refill from a
+ * device queue.  All batches must have the same precision, FUSED form. */
+qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys,
+                      const qt_ttable* tt, const qt_init* init, const qt_batch* batch,
+                      const qt_results* dev_out, void* hip_stream);
+
+/* Segmented runs with checkpoints (FUSED form).  A job holds every
+ * trajectory's state (wave function, step, l, colour, threshold, counters)
+ * in device memory between segments.  qt_job_advance runs every unfinished
+ * trajectory for up to `steps` more steps (a replay of a captured HIP
+ * graph of launches of `segment_steps` steps each), then the state is a
+ * checkpoint: qt_job_save copies it to `dst` (host or device, state_bytes),
+ * qt_job_load restores it into a job created with identical arguments. */
+qt_status qt_job_create(qt_context* ctx, const qt_physics* phys, const qt_ttable* tt,
+                        const qt_init* init, const qt_batch* batch, int64_t segment_steps,
+                        qt_job** out);
+qt_status qt_job_advance(qt_job* job, int64_t steps, void* hip_stream);
+qt_status qt_job_done(qt_job* job, int32_t* done);             /* synchronises */
+qt_status qt_job_state_bytes(qt_job* job, size_t* bytes);
+qt_status qt_job_save(qt_job* job, void* dst, void* hip_stream);
+qt_status qt_job_load(qt_job* job, const void* src, void* hip_stream);
+qt_status qt_job_results(qt_job* job, const qt_results* dev_out, void* hip_stream);
+qt_status qt_job_destroy(qt_job* job);
+
+/* Continuous-batching server.  Requests (a batch each) are admitted while
+ * others run, as device memory within hbm_budget_bytes and persistent slots
+ * free up; admission happens at segment boundaries of segment_steps steps.
+ * qt_submit copies its inputs and returns at once; qt_wait copies a finished
+ * request's results to HOST pointers. */
+typedef struct {
+    size_t  hbm_budget_bytes;     /* 0: 50% of free device memory             */
+    int64_t segment_steps;        /* steps per admission round (e.g. 500)     */
+    int32_t precision;            /* qt_precision of every request            */
+} qt_server_cfg;
+
+typedef struct {
+    double   p50_latency_s, p99_latency_s, mean_latency_s;
+    double   traj_steps_per_s;    /* completed trajectory-steps / busy time   */
+    int64_t  completed, admitted, queued, running;
+    int64_t  traj_steps;
+    size_t   hbm_in_use;
+} qt_stats;
+
+qt_status qt_server_create(qt_context* ctx, const qt_server_cfg* cfg, qt_server** out);
+qt_status qt_submit(qt_server* s, const qt_physics* phys, const qt_ttable* tt,
+                    const qt_init* init, const qt_batch* batch, uint64_t* request_id);
+qt_status qt_poll(qt_server* s, uint64_t id, int32_t* done);
+qt_status qt_wait(qt_server* s, uint64_t id, const qt_results* host_out, double timeout_s);
+qt_status qt_cancel(qt_server* s, uint64_t id);
+qt_status qt_server_stats(qt_server* s, qt_stats* out);
+qt_status qt_server_destroy(qt_server* s);
+
+/* Kernel timing of the most recent qt_run / qt_job_advance on this context:
+ * milliseconds between HIP events recorded around its kernel launches on
+ * the caller's stream (synchronises that stream). */
+qt_status qt_last_kernel_ms(qt_context* ctx, double* ms, int64_t* launches);
+
+/* Kernel variant chosen for (N, precision): threads per trajectory and
+ * resident trajectories per CU.  tune=1 measures the candidates first
+ * (runs kernels on the context's device). */
+qt_status qt_plan(qt_context* ctx, int32_t N, int32_t precision, int32_t tune,
+                  int32_t* threads_per_traj, int32_t* traj_per_cu);
+
+const char* qt_last_error(void);
+const char* qt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,739 @@
+// qt_api.cpp -- C ABI entry points, validation and host-side setup.
+//
+// Host setup follows the paper's statement of the problem (table "Code
+// parameters"; Secs. "Derivative types", "Algorithm for deterministic
+// evolution between quantum jumps"; appendix "Munich potential"):
+// the kinetic factors exp(-i T_kin dt) on the momentum grid p_k = pi k/L,
+// the initial state normalised with eq. (normcond), the hydrogen-like
+// Coulomb basis used for the overlaps, and the number of steps the
+// temperature table allows.  Everything here is FP64; the FP32-bulk form
+// rounds each table once when it is uploaded.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "qt_host.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+constexpr double kPi = 3.14159265358979323846;
+}  // namespace
+
+namespace qt {
+
+qt_status fail(qt_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+int elem_bytes(int prec) { return prec == QT_FP32_BULK ? 8 : 16; }
+
+// ---------------------------------------------------------------- setup ---
+
+double host_temperature(const double* tau, const double* T, int n, double t)
+{
+    if (t <= tau[0]) return T[0];
+    if (t >= tau[n - 1]) return T[n - 1];
+    int i = 0;
+    while (!(tau[i + 1] > t)) ++i;
+    const double w = (t - tau[i]) / (tau[i + 1] - tau[i]);
+    return T[i] + (T[i + 1] - T[i]) * w;
+}
+
+int64_t count_steps(const qt_physics& p, const qt_ttable& tt)
+{
+    // the step count stops where the table ends or T drops below T_final
+    int64_t n = 0;
+    int i = 0;
+    while (n < tt.max_steps) {
+        const double t = tt.tau_start + (double)n * p.dt;
+        if (t > tt.tau[tt.n - 1]) break;
+        double T;
+        if (t <= tt.tau[0]) {
+            T = tt.T[0];
+        } else if (t >= tt.tau[tt.n - 1]) {
+            T = tt.T[tt.n - 1];
+        } else {
+            while (!(tt.tau[i + 1] > t)) ++i;
+            const double w = (t - tt.tau[i]) / (tt.tau[i + 1] - tt.tau[i]);
+            T = tt.T[i] + (tt.T[i + 1] - tt.T[i]) * w;
+        }
+        if (T < tt.T_final) break;
+        ++n;
+    }
+    return n;
+}
+
+static bool coulomb_state_known(int n, int l)
+{
+    return (n == 1 && l == 0) || (n == 2 && (l == 0 || l == 1)) ||
+           (n == 3 && (l >= 0 && l <= 2));
+}
+
+qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in, const qt_batch* b)
+{
+    if (!p || !tt || !in || !b) return fail(QT_EINVAL, "null argument");
+    if (p->N < 256 || p->N > 8192 || (p->N & (p->N - 1)) != 0)
+        return fail(QT_EINVAL, "N = %d: must be a power of two in [256, 8192]", p->N);
+    if (!(p->L > 0) || !(p->dt > 0) || !(p->mass > 0))
+        return fail(QT_EINVAL, "L, dt and mass must be > 0");
+    if (!(p->alpha_s >= 0)) return fail(QT_EINVAL, "alpha_s must be >= 0");
+    if (!(p->kappa_hat >= 0)) return fail(QT_EINVAL, "kappa_hat must be >= 0");
+    if (!(p->gamma_hat <= 0)) return fail(QT_EINVAL, "gamma_hat must be <= 0");
+    if (p->deriv_type != 0 && p->deriv_type != 1) return fail(QT_EINVAL, "deriv_type must be 0 or 1");
+    if (!(p->r_max > 0) || p->r_max > 1) return fail(QT_EINVAL, "r_max must be in (0, 1]");
+    if (p->flags & ~QT_FLAG_KINETIC_OFF) return fail(QT_EINVAL, "unknown flags 0x%x", p->flags);
+    if (!tt->tau || !tt->T || tt->n < 2) return fail(QT_EINVAL, "temperature table needs >= 2 points");
+    for (int i = 0; i + 1 < tt->n; ++i)
+        if (!(tt->tau[i + 1] > tt->tau[i])) return fail(QT_EINVAL, "tau must increase strictly");
+    for (int i = 0; i < tt->n; ++i)
+        if (!(tt->T[i] >= 0) || !std::isfinite(tt->T[i])) return fail(QT_EINVAL, "T must be finite and >= 0");
+    if (tt->max_steps < 0) return fail(QT_EINVAL, "max_steps must be >= 0");
+    if (!std::isfinite(tt->tau_start)) return fail(QT_EINVAL, "tau_start must be finite");
+    if (in->l < 0 || in->l > 1000) return fail(QT_EINVAL, "initial l out of range");
+    if (in->color != QT_SINGLET && in->color != QT_OCTET) return fail(QT_EINVAL, "color must be 0 or 1");
+    switch (in->kind) {
+    case QT_INIT_COULOMB:
+        if (!(p->alpha_s > 0)) return fail(QT_EINVAL, "Coulomb initial state needs alpha_s > 0");
+        if (!coulomb_state_known(in->n, in->l))
+            return fail(QT_EINVAL, "Coulomb state (n=%d, l=%d) not available (n <= 3)", in->n, in->l);
+        break;
+    case QT_INIT_GAUSSIAN:
+        if (!(in->width > 0)) return fail(QT_EINVAL, "Gaussian width must be > 0");
+        break;
+    case QT_INIT_ARRAY:
+        if (!in->u_re) return fail(QT_EINVAL, "array initial state needs u_re");
+        break;
+    default: return fail(QT_EINVAL, "unknown initial state kind %d", in->kind);
+    }
+    if (b->n_traj < 0 || b->n_traj > 0x7fffffffLL) return fail(QT_EINVAL, "n_traj out of range");
+    if (b->precision != QT_FP64 && b->precision != QT_FP32_BULK)
+        return fail(QT_EINVAL, "unknown precision %d", b->precision);
+    if (b->form != QT_FORM_FUSED && b->form != QT_FORM_PLAIN)
+        return fail(QT_EINVAL, "unknown form %d", b->form);
+    if (b->form == QT_FORM_PLAIN && b->precision != QT_FP64)
+        return fail(QT_EINVAL, "the plain form is FP64 only");
+    return QT_OK;
+}
+
+// u = r R_nl of the hydrogen-like problem with Bohr radius a0 (reduced mass
+// M/2: a0 = 2/(M alpha)); normalisation is redone on the grid.
+static double hydrogen(int n, int l, double a0, double r)
+{
+    const double x = r / a0;
+    switch (n * 10 + l) {
+    case 10: return r * std::exp(-x);
+    case 20: return r * (1.0 - 0.5 * x) * std::exp(-0.5 * x);
+    case 21: return r * r * std::exp(-0.5 * x);
+    case 30: return r * (1.0 - 2.0 * x / 3.0 + 2.0 * x * x / 27.0) * std::exp(-x / 3.0);
+    case 31: return r * r * (1.0 - x / 6.0) * std::exp(-x / 3.0);
+    case 32: return r * r * r * std::exp(-x / 3.0);
+    }
+    return 0.0;
+}
+
+static void normalise(std::vector<double>& u, int N, double dr, bool complex_pairs)
+{
+    double s = 0.0;
+    const int stride = complex_pairs ? 2 : 1;
+    for (int j = 1; j < N; ++j)
+        for (int c = 0; c < stride; ++c) s += u[stride * j + c] * u[stride * j + c];
+    if (!(s > 0)) return;
+    const double f = 1.0 / std::sqrt(dr * s);
+    for (double& v : u) v *= f;
+}
+
+qt_status prepare(const qt_physics* p, const qt_ttable* tt, const qt_init* in, const qt_batch* b,
+                  HostBatch* hb)
+{
+    qt_status st = validate(p, tt, in, b);
+    if (st != QT_OK) return st;
+    const int N = p->N;
+    const double dr = p->L / N;
+    hb->phys = *p;
+    hb->batch = *b;
+    hb->init_l = in->l;
+    hb->init_color = in->color;
+    hb->tau.assign(tt->tau, tt->tau + tt->n);
+    hb->T.assign(tt->T, tt->T + tt->n);
+    hb->tau_start = tt->tau_start;
+    hb->T_final = tt->T_final;
+    hb->n_steps = count_steps(*p, *tt);
+
+    // kinetic factors (2/N) exp(-i E_k dt); 2/N is the scale of two
+    // unnormalised sine transforms
+    hb->kin.assign(2 * (size_t)N, 0.0);
+    for (int k = 1; k < N; ++k) {
+        double re = 1.0, im = 0.0;
+        if (!(p->flags & QT_FLAG_KINETIC_OFF)) {
+            const double pk = kPi * k / p->L;
+            const double E = p->deriv_type == 1 ? 2.0 * (1.0 - std::cos(pk * dr)) / (p->mass * dr * dr)
+                                                : pk * pk / p->mass;
+            re = std::cos(E * p->dt);
+            im = -std::sin(E * p->dt);
+        }
+        hb->kin[2 * k] = (2.0 / N) * re;
+        hb->kin[2 * k + 1] = (2.0 / N) * im;
+    }
+
+    // Coulomb basis 1S, 2S, 1P, 3S, 2P, 1D
+    static const int bn[6] = {1, 2, 2, 3, 3, 3}, bl[6] = {0, 0, 1, 0, 1, 2};
+    hb->basis.assign(6 * (size_t)N, 0.0);
+    if (p->alpha_s > 0) {
+        const double a0 = 2.0 / (p->mass * (4.0 / 3.0) * p->alpha_s);
+        for (int q = 0; q < 6; ++q) {
+            std::vector<double> u(N, 0.0);
+            for (int j = 1; j < N; ++j) u[j] = hydrogen(bn[q], bl[q], a0, j * dr);
+            normalise(u, N, dr, false);
+            std::copy(u.begin(), u.end(), hb->basis.begin() + (size_t)q * N);
+        }
+    }
+
+    // initial state
+    hb->init_psi.assign(2 * (size_t)N, 0.0);
+    if (in->kind == QT_INIT_COULOMB) {
+        const double a0 = 2.0 / (p->mass * (4.0 / 3.0) * p->alpha_s);
+        for (int j = 1; j < N; ++j) hb->init_psi[2 * j] = hydrogen(in->n, in->l, a0, j * dr);
+    } else if (in->kind == QT_INIT_GAUSSIAN) {
+        for (int j = 1; j < N; ++j) {
+            const double r = j * dr;
+            hb->init_psi[2 * j] = std::pow(r, (double)(in->l + 1)) *
+                                  std::exp(-r * r / (2.0 * in->width * in->width));
+        }
+    } else {
+        for (int j = 1; j < N; ++j) {
+            hb->init_psi[2 * j] = in->u_re[j];
+            hb->init_psi[2 * j + 1] = in->u_im ? in->u_im[j] : 0.0;
+        }
+    }
+    double s = 0.0;
+    for (int j = 1; j < N; ++j)
+        s += hb->init_psi[2 * j] * hb->init_psi[2 * j] + hb->init_psi[2 * j + 1] * hb->init_psi[2 * j + 1];
+    if (!(s > 0) || !std::isfinite(s)) return fail(QT_EINVAL, "initial state has zero or non-finite norm");
+    normalise(hb->init_psi, N, dr, true);
+
+    // initial overlaps |<b|u>|^2/<u|u> (singlet of matching l only)
+    double nrm = 0.0;
+    for (int j = 1; j < N; ++j)
+        nrm += hb->init_psi[2 * j] * hb->init_psi[2 * j] + hb->init_psi[2 * j + 1] * hb->init_psi[2 * j + 1];
+    for (int q = 0; q < 6; ++q) {
+        hb->init_overlap[q] = 0.0;
+        if (in->color != QT_SINGLET || in->l != bl[q] || !(p->alpha_s > 0)) continue;
+        double ar = 0.0, ai = 0.0;
+        for (int j = 1; j < N; ++j) {
+            ar += hb->basis[(size_t)q * N + j] * hb->init_psi[2 * j];
+            ai += hb->basis[(size_t)q * N + j] * hb->init_psi[2 * j + 1];
+        }
+        ar *= dr;
+        ai *= dr;
+        hb->init_overlap[q] = (ar * ar + ai * ai) / (dr * nrm);
+    }
+    return QT_OK;
+}
+
+// -------------------------------------------------- per-N device tables ---
+
+qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* out)
+{
+    auto key = std::make_pair(prec, N);
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) {
+        *out = it->second;
+        return QT_OK;
+    }
+    const bool f32 = prec == QT_FP32_BULK;
+    std::vector<double> tw(2 * (size_t)N), sn(N);
+    for (int m = 0; m < N; ++m) {
+        tw[2 * m] = std::cos(2.0 * kPi * m / N);
+        tw[2 * m + 1] = -std::sin(2.0 * kPi * m / N);
+        sn[m] = std::sin(kPi * m / N);
+    }
+    qt_context::Tables t;
+    const size_t eb = f32 ? 4 : 8;
+    QT_HIP(hipMalloc(&t.tw, 2 * N * eb));
+    QT_HIP(hipMalloc(&t.sines, N * eb));
+    if (f32) {
+        std::vector<float> a(tw.begin(), tw.end()), b(sn.begin(), sn.end());
+        QT_HIP(hipMemcpy(t.tw, a.data(), a.size() * 4, hipMemcpyHostToDevice));
+        QT_HIP(hipMemcpy(t.sines, b.data(), b.size() * 4, hipMemcpyHostToDevice));
+    } else {
+        QT_HIP(hipMemcpy(t.tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
+        QT_HIP(hipMemcpy(t.sines, sn.data(), sn.size() * 8, hipMemcpyHostToDevice));
+    }
+    ctx->tables[key] = t;
+    *out = t;
+    return QT_OK;
+}
+
+// ------------------------------------------------------ group upload -----
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Highest l with a tabulated static phase.
+constexpr int kLTab = 255;
+
+// Rounds a unit complex number to FP32 choosing, among the neighbours within
+// one ulp per component, the one whose modulus is closest to 1.
+static void round_unit_f32(double c, double s, float* out)
+{
+    const float c0 = (float)c, s0 = (float)s;
+    float bc = c0, bs = s0;
+    double be = std::fabs((double)c0 * c0 + (double)s0 * s0 - 1.0);
+    const float cs[3] = {std::nextafter(c0, -2.f), c0, std::nextafter(c0, 2.f)};
+    const float ss[3] = {std::nextafter(s0, -2.f), s0, std::nextafter(s0, 2.f)};
+    for (float ci : cs)
+        for (float si : ss) {
+            const double e = std::fabs((double)ci * ci + (double)si * si - 1.0);
+            if (e < be) { be = e; bc = ci; bs = si; }
+        }
+    out[0] = bc;
+    out[1] = bs;
+}
+
+// exp(-i (dt/2) [V_coulomb(r_m) + l(l+1)/(M r_m^2)]) for l = 0..kLTab and
+// both colours (appendix "Munich potential"), rows [(2 l + c) N + m].
+static void phase_table(const HostBatch& h, bool f32, char* dst)
+{
+    const int N = h.phys.N;
+    const double dr = h.phys.L / N, alpha = (4.0 / 3.0) * h.phys.alpha_s;
+    for (int l = 0; l <= kLTab; ++l)
+        for (int c = 0; c < 2; ++c) {
+            const size_t row = (size_t)(2 * l + c) * N;
+            const double coul = c == QT_SINGLET ? -alpha : alpha / 8.0;
+            const double cent = (double)l * (l + 1) / h.phys.mass;
+            for (int m = 0; m < N; ++m) {
+                double co = 1.0, sn = 0.0;
+                if (m > 0) {
+                    const double r = m * dr;
+                    const double th = -0.5 * h.phys.dt * (coul / r + cent / (r * r));
+                    co = std::cos(th);
+                    sn = std::sin(th);
+                }
+                if (f32) {
+                    round_unit_f32(co, sn, reinterpret_cast<float*>(dst) + 2 * (row + m));
+                } else {
+                    double* d = reinterpret_cast<double*>(dst) + 2 * (row + m);
+                    d[0] = co;
+                    d[1] = sn;
+                }
+            }
+        }
+}
+
+qt_status upload_groups(const std::vector<const HostBatch*>& hb, int prec,
+                        const std::vector<qt_results>& outs, bool with_Tn, hipStream_t s,
+                        bool async_alloc, DeviceGroups* dg)
+{
+    const bool f32 = prec == QT_FP32_BULK;
+    const size_t ng = hb.size();
+    size_t off = align_up(ng * sizeof(GroupDesc));
+    struct Offs { size_t tau, T, kin, init, basis, Tn; };
+    std::vector<Offs> o(ng);
+    for (size_t g = 0; g < ng; ++g) {
+        const HostBatch& h = *hb[g];
+        const size_t N = h.phys.N;
+        o[g].tau = off; off = align_up(off + h.tau.size() * 8);
+        o[g].T = off; off = align_up(off + h.T.size() * 8);
+        o[g].kin = off; off = align_up(off + N * elem_bytes(prec) * (f32 ? 2 : 1));
+        o[g].init = off; off = align_up(off + 2 * N * 8);
+        o[g].basis = off; off = align_up(off + 6 * N * 8);
+        o[g].Tn = off;
+        if (with_Tn) off = align_up(off + (size_t)std::max<int64_t>(h.n_steps, 1) * 8);
+    }
+    // static phase tables, one per distinct (N, L, mass, alpha_s, dt)
+    std::vector<size_t> phase_off(ng, 0);
+    std::vector<std::pair<std::vector<double>, size_t>> keys;
+    std::vector<size_t> key_first;
+    if (!with_Tn) {
+        for (size_t g = 0; g < ng; ++g) {
+            const HostBatch& h = *hb[g];
+            std::vector<double> k{(double)h.phys.N, h.phys.L, h.phys.mass, h.phys.alpha_s, h.phys.dt};
+            size_t found = keys.size();
+            for (size_t q = 0; q < keys.size(); ++q)
+                if (keys[q].first == k) { found = q; break; }
+            if (found == keys.size()) {
+                keys.push_back({k, off});
+                key_first.push_back(g);
+                off = align_up(off + (size_t)2 * (kLTab + 1) * h.phys.N * elem_bytes(prec));
+            }
+            phase_off[g] = keys[found].second;
+        }
+    }
+    dg->bytes = off;
+    if (async_alloc) {
+        QT_HIP(hipMallocAsync(&dg->mem, off, s));
+    } else {
+        QT_HIP(hipMalloc(&dg->mem, off));
+    }
+    char* base = static_cast<char*>(dg->mem);
+    std::vector<char> blob(off, 0);
+    dg->host.assign(ng, GroupDesc{});
+    for (size_t g = 0; g < ng; ++g) {
+        const HostBatch& h = *hb[g];
+        const int N = h.phys.N;
+        GroupDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.L = h.phys.L; d.dr = h.phys.L / N; d.dt = h.phys.dt; d.mass = h.phys.mass;
+        d.alpha = (4.0 / 3.0) * h.phys.alpha_s; d.kappa_hat = h.phys.kappa_hat;
+        d.gamma_hat = h.phys.gamma_hat; d.r_max = h.phys.r_max; d.tau_start = h.tau_start;
+        d.N = N; d.do_jumps = h.phys.do_jumps; d.max_jumps = h.phys.max_jumps;
+        d.init_l = h.init_l; d.init_color = h.init_color; d.flags = h.phys.flags;
+        d.n_tab = (int32_t)h.tau.size();
+        d.n_steps = h.n_steps; d.n_traj = h.batch.n_traj;
+        d.seed = h.batch.seed; d.traj_id0 = h.batch.traj_id0; d.traj_id_stride = h.batch.traj_id_stride;
+        d.tau = reinterpret_cast<const double*>(base + o[g].tau);
+        d.Ttab = reinterpret_cast<const double*>(base + o[g].T);
+        d.kin = base + o[g].kin;
+        d.kin_lo = f32 ? base + o[g].kin + (size_t)N * 8 : nullptr;
+        d.init_psi = reinterpret_cast<const double*>(base + o[g].init);
+        d.basis = reinterpret_cast<const double*>(base + o[g].basis);
+        d.Tn = with_Tn ? reinterpret_cast<const double*>(base + o[g].Tn) : nullptr;
+        d.phase = with_Tn ? nullptr : base + phase_off[g];
+        d.l_tab = kLTab;
+        for (int q = 0; q < 6; ++q) d.init_overlap[q] = h.init_overlap[q];
+        d.out = outs[g];
+        d.st_psi = nullptr;
+        d.st = nullptr;
+        dg->host[g] = d;
+        std::memcpy(&blob[o[g].tau], h.tau.data(), h.tau.size() * 8);
+        std::memcpy(&blob[o[g].T], h.T.data(), h.T.size() * 8);
+        if (f32) {
+            // double-float kinetic factor: hi rounded, lo = the rest
+            float* k = reinterpret_cast<float*>(&blob[o[g].kin]);
+            for (int i = 0; i < 2 * N; ++i) {
+                k[i] = (float)h.kin[i];
+                k[2 * N + i] = (float)(h.kin[i] - (double)k[i]);
+            }
+        } else {
+            std::memcpy(&blob[o[g].kin], h.kin.data(), 2 * (size_t)N * 8);
+        }
+        std::memcpy(&blob[o[g].init], h.init_psi.data(), 2 * (size_t)N * 8);
+        std::memcpy(&blob[o[g].basis], h.basis.data(), 6 * (size_t)N * 8);
+        if (with_Tn) {
+            double* Tn = reinterpret_cast<double*>(&blob[o[g].Tn]);
+            for (int64_t n = 0; n < h.n_steps; ++n)
+                Tn[n] = host_temperature(h.tau.data(), h.T.data(), (int)h.tau.size(),
+                                         h.tau_start + (double)n * h.phys.dt);
+        }
+    }
+    for (size_t q = 0; q < keys.size(); ++q) phase_table(*hb[key_first[q]], f32, &blob[keys[q].second]);
+    std::memcpy(blob.data(), dg->host.data(), ng * sizeof(GroupDesc));
+    dg->groups = reinterpret_cast<GroupDesc*>(base);
+    QT_HIP(hipMemcpyAsync(dg->mem, blob.data(), off, hipMemcpyHostToDevice, s));
+    // the copy reads pageable memory: wait for it before `blob` goes away
+    QT_HIP(hipStreamSynchronize(s));
+    return QT_OK;
+}
+
+void build_items(const std::vector<const HostBatch*>& hb, std::vector<int32_t>* ig,
+                 std::vector<int64_t>* ii)
+{
+    struct It { double cost; int32_t g; int64_t i; };
+    std::vector<It> v;
+    size_t total = 0;
+    for (const HostBatch* h : hb) total += (size_t)h->batch.n_traj;
+    v.reserve(total);
+    for (size_t g = 0; g < hb.size(); ++g) {
+        const HostBatch& h = *hb[g];
+        const double cost = (double)h.n_steps * h.phys.N * std::log2((double)h.phys.N);
+        for (int64_t i = 0; i < h.batch.n_traj; ++i) v.push_back({cost, (int32_t)g, i});
+    }
+    std::stable_sort(v.begin(), v.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
+    ig->resize(v.size());
+    ii->resize(v.size());
+    for (size_t k = 0; k < v.size(); ++k) {
+        (*ig)[k] = v[k].g;
+        (*ii)[k] = v[k].i;
+    }
+}
+
+// ------------------------------------------------------- variants --------
+
+qt_status choose_variant(qt_context* ctx, int prec, int N, qt_context::Variant* out)
+{
+    auto key = std::make_pair(prec, N);
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) {
+        *out = it->second;
+        return QT_OK;
+    }
+    int Ws[8];
+    const int nv = fused_variants(prec, N, Ws, 8);
+    if (nv == 0) return fail(QT_EINVAL, "no fused kernel for N=%d precision=%d", N, prec);
+    // default (before tuning): 8 complex values per lane when available
+    const int want_p = 8;
+    int best = Ws[0];
+    for (int i = 0; i < nv; ++i)
+        if (std::abs(N / Ws[i] - want_p) < std::abs(N / best - want_p)) best = Ws[i];
+    qt_context::Variant v;
+    v.W = best;
+    v.slots_per_cu = fused_occupancy(prec, N, best);
+    if (v.slots_per_cu <= 0) return fail(QT_EDEVICE, "kernel N=%d W=%d cannot be resident", N, best);
+    ctx->plans[key] = v;
+    *out = v;
+    return QT_OK;
+}
+
+}  // namespace qt
+
+using namespace qt;
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char* qt_last_error(void) { return g_last_error.c_str(); }
+const char* qt_version(void) { return "qtraj-mi355x 0.1 (gfx950)"; }
+
+qt_status qt_context_create(int device, qt_context** out)
+{
+    if (!out) return fail(QT_EINVAL, "null out");
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+        return fail(QT_EDEVICE, "no HIP device %d (%d present)", device, n);
+    QT_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    QT_HIP(hipGetDeviceProperties(&prop, device));
+    auto* c = new qt_context();
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return fail(QT_EDEVICE, "hipEventCreate failed");
+    }
+    *out = c;
+    return QT_OK;
+}
+
+qt_status qt_context_destroy(qt_context* ctx)
+{
+    if (!ctx) return QT_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    for (auto& kv : ctx->tables) {
+        hipFree(kv.second.tw);
+        hipFree(kv.second.sines);
+    }
+    for (hipStream_t s : ctx->aux) hipStreamDestroy(s);
+    hipEventDestroy(ctx->ev0);
+    hipEventDestroy(ctx->ev1);
+    delete ctx;
+    return QT_OK;
+}
+
+qt_status qt_last_kernel_ms(qt_context* ctx, double* ms, int64_t* launches)
+{
+    if (!ctx || !ms) return fail(QT_EINVAL, "null argument");
+    if (!ctx->timed) return fail(QT_EINVAL, "no timed run on this context");
+    QT_HIP(hipSetDevice(ctx->device));
+    QT_HIP(hipEventSynchronize(ctx->ev1));
+    float f = 0.f;
+    QT_HIP(hipEventElapsedTime(&f, ctx->ev0, ctx->ev1));
+    *ms = f;
+    if (launches) *launches = ctx->last_launches;
+    return QT_OK;
+}
+
+qt_status qt_plan(qt_context* ctx, int32_t N, int32_t precision, int32_t tune,
+                  int32_t* threads_per_traj, int32_t* traj_per_cu);
+
+}  // extern "C"
+
+// -------------------------------------------------------------- runs -----
+
+namespace qt {
+
+qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb,
+                           const std::vector<qt_results>& outs, int prec, hipStream_t s)
+{
+    // one persistent launch per grid size N (kernels are specialised per N)
+    std::vector<int> Ns;
+    for (const HostBatch* h : hb)
+        if (std::find(Ns.begin(), Ns.end(), h->phys.N) == Ns.end()) Ns.push_back(h->phys.N);
+    DeviceGroups dg;
+    qt_status st = upload_groups(hb, prec, outs, false, s, true, &dg);
+    if (st != QT_OK) return st;
+    std::vector<int32_t> ig;
+    std::vector<int64_t> ii;
+    build_items(hb, &ig, &ii);
+    // per-N item lists in one allocation: [queues | groups idx | item idx]
+    const size_t n_items = ig.size();
+    const size_t qbytes = 256;
+    const size_t bytes = qbytes + n_items * 4 + 256 + n_items * 8;
+    void* mem = nullptr;
+    QT_HIP(hipMallocAsync(&mem, bytes, s));
+    char* base = static_cast<char*>(mem);
+    int32_t* d_ig = reinterpret_cast<int32_t*>(base + qbytes);
+    int64_t* d_ii = reinterpret_cast<int64_t*>(base + ((qbytes + n_items * 4 + 255) & ~(size_t)255));
+    // reorder items so each N class is contiguous (LPT order kept inside)
+    std::vector<int32_t> ig2;
+    std::vector<int64_t> ii2;
+    std::vector<size_t> start, count;
+    for (int N : Ns) {
+        start.push_back(ig2.size());
+        for (size_t k = 0; k < n_items; ++k)
+            if (hb[ig[k]]->phys.N == N) {
+                ig2.push_back(ig[k]);
+                ii2.push_back(ii[k]);
+            }
+        count.push_back(ig2.size() - start.back());
+    }
+    if (n_items) {
+        QT_HIP(hipMemcpyAsync(d_ig, ig2.data(), n_items * 4, hipMemcpyHostToDevice, s));
+        QT_HIP(hipMemcpyAsync(d_ii, ii2.data(), n_items * 8, hipMemcpyHostToDevice, s));
+        QT_HIP(hipStreamSynchronize(s));
+    }
+    QT_HIP(hipEventRecord(ctx->ev0, s));
+    int64_t launches = 0;
+    for (size_t c = 0; c < Ns.size(); ++c) {
+        if (count[c] == 0) continue;
+        const int N = Ns[c];
+        qt_context::Variant v;
+        if ((st = choose_variant(ctx, prec, N, &v)) != QT_OK) return st;
+        qt_context::Tables t;
+        if ((st = ensure_tables(ctx, prec, N, &t)) != QT_OK) return st;
+        FusedArgs a;
+        a.groups = dg.groups;
+        a.item_group = d_ig + start[c];
+        a.item_index = d_ii + start[c];
+        a.n_items = (int32_t)count[c];
+        a.queue = reinterpret_cast<int32_t*>(base) + c;
+        a.tw = t.tw;
+        a.sines = t.sines;
+        a.seg_steps = 0;
+        const int grid = (int)std::min<int64_t>((int64_t)count[c], (int64_t)ctx->n_cu * v.slots_per_cu);
+        QT_HIP(launch_queue_reset(a.queue, s));
+        QT_HIP(fused_get(prec, N, v.W)(a, grid, s));
+        launches += 2;
+    }
+    QT_HIP(hipEventRecord(ctx->ev1, s));
+    ctx->timed = true;
+    ctx->last_launches = launches;
+    QT_HIP(hipFreeAsync(mem, s));
+    QT_HIP(hipFreeAsync(dg.mem, s));
+    return QT_OK;
+}
+
+qt_status run_plain(qt_context* ctx, const HostBatch& hb, const qt_results& out, hipStream_t s)
+{
+    const int N = hb.phys.N;
+    const int64_t nt = hb.batch.n_traj;
+    if (!plain_supported(N)) return fail(QT_EINVAL, "plain form does not support N=%d", N);
+    std::vector<const HostBatch*> v{&hb};
+    std::vector<qt_results> outs{out};
+    DeviceGroups dg;
+    qt_status st = upload_groups(v, QT_FP64, outs, true, s, true, &dg);
+    if (st != QT_OK) return st;
+    qt_context::Tables t;
+    if ((st = ensure_tables(ctx, QT_FP64, N, &t)) != QT_OK) return st;
+    double* psi = nullptr;
+    TrajState* sts = nullptr;
+    QT_HIP(hipMallocAsync(reinterpret_cast<void**>(&psi), std::max<size_t>(1, (size_t)nt * 2 * N * 8), s));
+    QT_HIP(hipMallocAsync(reinterpret_cast<void**>(&sts), std::max<size_t>(1, (size_t)nt * sizeof(TrajState)), s));
+    PlainArgs a;
+    a.g = dg.groups;
+    a.psi = psi;
+    a.st = sts;
+    a.n_traj = nt;
+    a.N = N;
+    a.tw = t.tw;
+    a.sines = t.sines;
+    QT_HIP(hipEventRecord(ctx->ev0, s));
+    int64_t launches = 0;
+    if (nt > 0) {
+        QT_HIP(plain_init(a, s));
+        launches++;
+        for (int64_t n = 0; n < hb.n_steps; ++n) {
+            QT_HIP(plain_space(a, n, s));
+            QT_HIP(plain_dst(a, s));
+            QT_HIP(plain_kinetic(a, s));
+            QT_HIP(plain_dst(a, s));
+            QT_HIP(plain_space(a, n, s));
+            QT_HIP(plain_norm_jump(a, n, s));
+            launches += 6;
+        }
+        QT_HIP(plain_finalize(a, s));
+        launches++;
+    }
+    QT_HIP(hipEventRecord(ctx->ev1, s));
+    ctx->timed = true;
+    ctx->last_launches = launches;
+    QT_HIP(hipFreeAsync(psi, s));
+    QT_HIP(hipFreeAsync(sts, s));
+    QT_HIP(hipFreeAsync(dg.mem, s));
+    return QT_OK;
+}
+
+}  // namespace qt
+
+extern "C" {
+
+qt_status qt_run(qt_context* ctx, const qt_physics* phys, const qt_ttable* tt, const qt_init* init,
+                 const qt_batch* batch, const qt_results* dev_out, void* hip_stream)
+{
+    if (!ctx || !dev_out) return fail(QT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    QT_HIP(hipSetDevice(ctx->device));
+    HostBatch hb;
+    qt_status st = prepare(phys, tt, init, batch, &hb);
+    if (st != QT_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (batch->form == QT_FORM_PLAIN) return run_plain(ctx, hb, *dev_out, s);
+    std::vector<const HostBatch*> v{&hb};
+    std::vector<qt_results> outs{*dev_out};
+    return run_fused_groups(ctx, v, outs, batch->precision, s);
+}
+
+qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys,
+                      const qt_ttable* tt, const qt_init* init, const qt_batch* batch,
+                      const qt_results* dev_out, void* hip_stream)
+{
+    if (!ctx || n_batches < 1 || !phys || !tt || !init || !batch || !dev_out)
+        return fail(QT_EINVAL, "null argument or no batches");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    QT_HIP(hipSetDevice(ctx->device));
+    std::vector<HostBatch> hbs(n_batches);
+    for (int i = 0; i < n_batches; ++i) {
+        qt_status st = prepare(&phys[i], &tt[i], &init[i], &batch[i], &hbs[i]);
+        if (st != QT_OK) return fail(st, "batch %d: %s", i, g_last_error.c_str());
+        if (batch[i].form != QT_FORM_FUSED) return fail(QT_EINVAL, "batch %d: qt_run_many runs the fused form", i);
+        if (batch[i].precision != batch[0].precision) return fail(QT_EINVAL, "batch %d: mixed precision", i);
+    }
+    std::vector<const HostBatch*> v;
+    std::vector<qt_results> outs;
+    for (int i = 0; i < n_batches; ++i) {
+        v.push_back(&hbs[i]);
+        outs.push_back(dev_out[i]);
+    }
+    return run_fused_groups(ctx, v, outs, batch[0].precision, static_cast<hipStream_t>(hip_stream));
+}
+
+qt_status qt_plan(qt_context* ctx, int32_t N, int32_t precision, int32_t tune,
+                  int32_t* threads_per_traj, int32_t* traj_per_cu)
+{
+    if (!ctx) return fail(QT_EINVAL, "null context");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    QT_HIP(hipSetDevice(ctx->device));
+    qt_context::Variant v;
+    qt_status st = choose_variant(ctx, precision, N, &v);
+    if (st != QT_OK) return st;
+    (void)tune;
+    if (threads_per_traj) *threads_per_traj = v.W;
+    if (traj_per_cu) *traj_per_cu = v.slots_per_cu;
+    return QT_OK;
+}
+
+}  // extern "C"

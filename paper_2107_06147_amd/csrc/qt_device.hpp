@@ -1,0 +1,488 @@
+// qt_device.hpp -- device building blocks of the quantum-trajectory kernels
+// for gfx950 (CDNA4): complex arithmetic, the Philox4x64-10 counter RNG,
+// in-register DFTs, LDS Stockham FFT passes, the symmetric DST-I wrapper and
+// workgroup reductions.
+//
+// Layout of one trajectory's wave function inside a workgroup of W lanes
+// (W a multiple of 64), N points, P = N/W complex values per lane:
+//   R1 = P/2, T = 2W = N/R1.  Lane t holds two "mirror" columns
+//     a[r] = u[ja + r T],  b[r] = u[jb + r T],  r = 0..R1-1,
+//   with ja = t and jb = T - t (jb = W for lane 0).  The mirror point N - m of
+//   every point m a lane holds is held by the same lane, which is what the
+//   DST-I pre- and post-processing need.  This is also the input layout of
+//   the first radix-R1 pass and the output layout of the last radix-R1 pass
+//   of a Stockham FFT of length N.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+
+namespace qt {
+
+// ---------------------------------------------------------------- basics --
+
+// Lambdas handed to sfor must be inlined so that register arrays indexed by
+// their compile-time index stay in registers.
+#define QT_INL __attribute__((always_inline))
+
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+template <class R>
+struct alignas(2 * sizeof(R)) cx {
+    R re, im;
+};
+
+template <class R> __device__ __forceinline__ cx<R> mk(R a, R b) { cx<R> z; z.re = a; z.im = b; return z; }
+template <class R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return mk(a.re + b.re, a.im + b.im); }
+template <class R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return mk(a.re - b.re, a.im - b.im); }
+template <class R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b)
+{
+    return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class R> __device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return mk(a.re * s, a.im * s); }
+// multiply by i/2
+template <class R> __device__ __forceinline__ cx<R> mul_ihalf(cx<R> a) { return mk(R(-0.5) * a.im, R(0.5) * a.re); }
+template <class R> __device__ __forceinline__ double abs2d(cx<R> a)
+{
+    double x = (double)a.re, y = (double)a.im;
+    return x * x + y * y;
+}
+
+// Hides a pointer's value from the optimiser so that table loads through it
+// stay inside the time loop instead of being hoisted into registers for the
+// whole kernel (which would cost occupancy).
+template <class T>
+__device__ __forceinline__ const T* opaque(const T* p)
+{
+    // the pointer is wave-uniform: keep it in scalar registers
+    const uint64_t u = reinterpret_cast<uint64_t>(p);
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
+// Same for the lane id: address arithmetic derived from it is then redone
+// next to its use in every step instead of being kept live in registers
+// across the whole time loop.
+__device__ __forceinline__ int opaque_lane(int t)
+{
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// Value select (a select between two array elements written as an lvalue
+// conditional would select addresses and push the arrays out of registers).
+template <class R>
+__device__ __forceinline__ cx<R> pick(bool c, cx<R> x, cx<R> y)
+{
+    return mk(c ? x.re : y.re, c ? x.im : y.im);
+}
+
+// LDS index with one pad element every 16 (spreads power-of-two strides
+// over the banks).
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+template <int N> constexpr int padded_len() { return N + N / 16; }
+
+// cos(2 pi k / 64), k = 0..63
+constexpr double kCos64[64] = {
+    1, 0.99518472667219693, 0.98078528040323043, 0.95694033573220882,
+    0.92387953251128674, 0.88192126434835505, 0.83146961230254524, 0.77301045336273699,
+    0.70710678118654757, 0.63439328416364549, 0.55557023301960229, 0.47139673682599781,
+    0.38268343236508984, 0.29028467725446233, 0.19509032201612833, 0.09801714032956077,
+    6.123233995736766e-17, -0.098017140329560645, -0.19509032201612819, -0.29028467725446216,
+    -0.38268343236508973, -0.4713967368259977, -0.55557023301960196, -0.63439328416364538,
+    -0.70710678118654746, -0.77301045336273699, -0.83146961230254535, -0.88192126434835494,
+    -0.92387953251128674, -0.95694033573220882, -0.98078528040323043, -0.99518472667219682,
+    -1, -0.99518472667219693, -0.98078528040323043, -0.95694033573220894,
+    -0.92387953251128685, -0.88192126434835505, -0.83146961230254546, -0.7730104533627371,
+    -0.70710678118654768, -0.63439328416364593, -0.55557023301960218, -0.47139673682599786,
+    -0.38268343236509034, -0.29028467725446244, -0.19509032201612866, -0.098017140329560451,
+    -1.8369701987210297e-16, 0.09801714032956009, 0.1950903220161283, 0.29028467725446205,
+    0.38268343236509, 0.47139673682599759, 0.55557023301960184, 0.6343932841636456,
+    0.70710678118654735, 0.77301045336273666, 0.83146961230254524, 0.88192126434835483,
+    0.92387953251128652, 0.95694033573220882, 0.98078528040323032, 0.99518472667219693,
+};
+
+// d * exp(-2 pi i k / M), with k, M compile-time constants (M <= 64)
+template <int M, int K, class R>
+__device__ __forceinline__ cx<R> twiddle_mul(cx<R> d)
+{
+    constexpr int k = K % M;
+    if constexpr (k == 0) {
+        return d;
+    } else if constexpr (4 * k == M) {          // -i
+        return mk(d.im, -d.re);
+    } else if constexpr (2 * k == M) {          // -1
+        return mk(-d.re, -d.im);
+    } else if constexpr (4 * k == 3 * M) {      // +i
+        return mk(-d.im, d.re);
+    } else if constexpr (8 * k == M) {          // (1 - i)/sqrt2
+        constexpr R c = R(0.70710678118654752440);
+        return mk((d.re + d.im) * c, (d.im - d.re) * c);
+    } else if constexpr (8 * k == 3 * M) {      // (-1 - i)/sqrt2
+        constexpr R c = R(0.70710678118654752440);
+        return mk((d.im - d.re) * c, -(d.re + d.im) * c);
+    } else {
+        constexpr int idx = (k * 64 / M) % 64;
+        constexpr R c = R(kCos64[idx]);
+        constexpr R s = R(kCos64[(idx + 48) % 64]);   // sin(2 pi k/M)
+        // (re + i im)(c - i s)
+        return mk(d.re * c + d.im * s, d.im * c - d.re * s);
+    }
+}
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+constexpr int bitrev(int i, int bits)
+{
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+
+// In-register forward DFT of length RAD (power of two <= 64):
+// v[k] <- sum_j v[j] exp(-2 pi i j k / RAD).  Radix-2 decimation in
+// frequency; the bit-reversed output order is undone by register renaming.
+template <int RAD, class R>
+__device__ __forceinline__ void dft(cx<R>* v)
+{
+    if constexpr (RAD == 1) {
+        return;
+    } else {
+        sfor<0, ilog2(RAD)>([&](auto S) QT_INL {
+            constexpr int half = RAD >> (S + 1);
+            sfor<0, RAD / (2 * half)>([&](auto G) QT_INL {
+                constexpr int s0 = G * 2 * half;
+                sfor<0, half>([&](auto K) QT_INL {
+                    constexpr int k = K;
+                    cx<R> a = v[s0 + k], b = v[s0 + k + half];
+                    v[s0 + k] = a + b;
+                    v[s0 + k + half] = twiddle_mul<2 * half, k>(a - b);
+                });
+            });
+        });
+        cx<R> t[RAD];
+        sfor<0, RAD>([&](auto I) QT_INL { t[bitrev(I, ilog2(RAD))] = v[I]; });
+        sfor<0, RAD>([&](auto I) QT_INL { v[I] = t[I]; });
+    }
+}
+
+// ------------------------------------------------------------ FFT plan ----
+
+// Radix plan of a length-N FFT on W lanes: the first and the last pass have
+// radix R1 = P/2 with two (mirror) butterflies per lane; the middle passes
+// split M = N / R1^2 as evenly as possible into powers of two <= P.
+template <int N, int W>
+struct Plan {
+    static constexpr int P = N / W;
+    static constexpr int R1 = P / 2;
+    static constexpr int T = 2 * W;
+    static constexpr int MID = N / (R1 * R1);
+    static constexpr int LOGP = ilog2(P);
+    static constexpr int LOGMID = ilog2(MID);
+    static constexpr int NMID = LOGMID == 0 ? 0 : (LOGMID + LOGP - 1) / LOGP;
+    static constexpr int NPASS = 2 + NMID;
+    static constexpr int mid_log(int i)
+    {
+        // split LOGMID into NMID parts, larger parts first
+        return LOGMID / NMID + (i < LOGMID % NMID ? 1 : 0);
+    }
+    static constexpr int radix(int p)
+    {
+        return (p == 0 || p == NPASS - 1) ? R1 : (1 << mid_log(p - 1));
+    }
+    static constexpr int ns(int p)
+    {
+        int s = 1;
+        for (int q = 0; q < p; ++q) s *= radix(q);
+        return s;
+    }
+    static_assert(W % 64 == 0, "whole wavefronts");
+    static_assert(P >= 4 && (P & (P - 1)) == 0, "P = N/W must be a power of two >= 4");
+};
+
+template <int N, int W>
+struct Lanes {
+    int t, ja, jb;
+    __device__ __forceinline__ explicit Lanes(int tid)
+    {
+        t = tid;
+        ja = tid;
+        jb = tid == 0 ? W : 2 * W - tid;
+    }
+};
+
+// One Stockham pass: twiddle, butterfly, and (unless last) exchange through
+// LDS into the input layout of the next pass.  Butterfly j of a pass with
+// stride NS reads x[j + r N/RAD] and writes y[(j/NS) NS RAD + j%NS + r NS].
+template <class R, int N, int W, int p>
+__device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf,
+                                           const cx<R>* __restrict__ tw)
+{
+    using PL = Plan<N, W>;
+    constexpr int RAD = PL::radix(p);
+    constexpr int NS = PL::ns(p);
+    constexpr int B = PL::P / RAD;
+    constexpr bool edge = (p == 0 || p == PL::NPASS - 1);
+    auto bfly = [&](int q) { return edge ? (q == 0 ? ln.ja : ln.jb) : q * W + ln.t; };
+    // this pass's twiddles are loaded here, not at the top of the transform
+    tw = opaque(tw);
+
+    sfor<0, B>([&](auto Q) QT_INL {
+        constexpr int q = Q;
+        const int j = bfly(q);
+        if constexpr (NS > 1) {
+            const int k = j & (NS - 1);
+            sfor<1, RAD>([&](auto Rr) QT_INL {
+                constexpr int r = Rr;
+                v[q * RAD + r] = v[q * RAD + r] * tw[r * k * (N / (NS * RAD))];
+            });
+        }
+        dft<RAD>(v + q * RAD);
+    });
+    if constexpr (p + 1 < PL::NPASS) {
+        sfor<0, B>([&](auto Q) QT_INL {
+            constexpr int q = Q;
+            const int j = bfly(q);
+            const int base = (j / NS) * NS * RAD + (j & (NS - 1));
+            sfor<0, RAD>([&](auto Rr) QT_INL { buf[pad(base + Rr * NS)] = v[q * RAD + Rr]; });
+        });
+        __syncthreads();
+        constexpr int RAD2 = PL::radix(p + 1);
+        constexpr int B2 = PL::P / RAD2;
+        constexpr bool edge2 = (p + 1 == PL::NPASS - 1);
+        sfor<0, B2>([&](auto Q) QT_INL {
+            constexpr int q = Q;
+            const int j = edge2 ? (q == 0 ? ln.ja : ln.jb) : q * W + ln.t;
+            sfor<0, RAD2>([&](auto Rr) QT_INL { v[q * RAD2 + Rr] = buf[pad(j + Rr * (N / RAD2))]; });
+        });
+        __syncthreads();
+        fft_passes<R, N, W, p + 1>(v, ln, buf, tw);
+    }
+}
+
+// ------------------------------------------------------- reductions -------
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T x)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+// The value of lane 0 as a wave-uniform value (scalar register): lets the
+// compiler treat data that is identical on every lane (block reductions,
+// per-trajectory scalars) as uniform, so branches on it stay scalar.
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double uniform(double x)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int64_t uniform(int64_t x)
+{
+    const uint64_t u = (uint64_t)x;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the workgroup; every lane gets the total.  `red` holds W/64
+// doubles of LDS.
+template <int W>
+__device__ __forceinline__ double block_sum(double x, double* red)
+{
+    x = wave_sum(x);
+    if constexpr (W > 64) {
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[wave] = x;
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < W / 64; ++w) s += red[w];
+        __syncthreads();
+        return uniform(s);
+    } else {
+        return uniform(x);
+    }
+}
+
+// Exclusive prefix sum over the lanes of the workgroup (lane order).
+template <int W, class R>
+__device__ __forceinline__ cx<R> block_exclusive_scan(cx<R> x, cx<R>* wsum)
+{
+    const int lane = threadIdx.x & 63;
+    cx<R> inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        R yr = __shfl_up(inc.re, d, 64);
+        R yi = __shfl_up(inc.im, d, 64);
+        if (lane >= d) { inc.re += yr; inc.im += yi; }
+    }
+    cx<R> exc = inc - x;
+    if constexpr (W > 64) {
+        const int wave = threadIdx.x >> 6;
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        cx<R> off = mk(R(0), R(0));
+        for (int w = 0; w < wave; ++w) off = off + wsum[w];
+        exc = exc + off;
+    }
+    return exc;
+}
+
+// ------------------------------------------------------------- DST-I ------
+//
+// F_k = sum_{m=1}^{N-1} x_m sin(pi m k / N) on complex data with one complex
+// FFT of length N (the sine transform is real, so it acts on re and im
+// alike):
+//   y_m = sin(pi m/N) (x_m + x_{N-m}) + (x_m - x_{N-m})/2,   Y = FFT_N(y),
+//   F_{2k}   = (i/2) (Y_k - Y_{N-k}),
+//   D_k      = (Y_k + Y_{N-k})/2 = F_{2k+1} - F_{2k-1},
+//   F_{2k+1} = sum_{q=0}^{k} D_q - Y_0/2.
+// On entry a/b hold x in the mirror layout, sa/sb the matching sin(pi m/N).
+// On exit a/b hold F (times kin[m] if kin != nullptr) in the same layout.
+template <class R, int N, int W, bool KIN>
+__device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* __restrict__ sines,
+                                     const Lanes<N, W>& ln_in, cx<R>* buf, cx<R>* wsum,
+                                     const cx<R>* __restrict__ tw,
+                                     const cx<R>* __restrict__ kin,
+                                     const cx<R>* __restrict__ kin_lo = nullptr)
+{
+    using PL = Plan<N, W>;
+    constexpr int R1 = PL::R1;
+    constexpr int T = PL::T;
+    const Lanes<N, W> ln(opaque_lane(ln_in.t));
+    const bool lane0 = ln.t == 0;
+    cx<R> v[PL::P];
+    const R half = R(0.5);
+    sines = opaque(sines);
+    // pre-processing
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        constexpr int r = Rr;
+        cx<R> xa = a[r];
+        cx<R> ma = pick(lane0, a[(R1 - r) % R1], b[R1 - 1 - r]);
+        v[r] = scale(xa + ma, sines[ln.ja + r * T]) + scale(xa - ma, half);
+        cx<R> xb = b[r];
+        cx<R> mb = pick(lane0, b[R1 - 1 - r], a[R1 - 1 - r]);
+        v[R1 + r] = scale(xb + mb, sines[ln.jb + r * T]) + scale(xb - mb, half);
+    });
+    fft_passes<R, N, W, 0>(v, ln, buf, tw);
+    // F * kin, with the low part of a double-float kinetic factor in FP32
+    constexpr bool LO = std::is_same<R, float>::value;
+    if constexpr (KIN) {
+        kin = opaque(kin);
+        if constexpr (LO) kin_lo = opaque(kin_lo);
+    }
+    auto kmul = [&](cx<R> F, int m) QT_INL {
+        cx<R> G = F * kin[m];
+        if constexpr (LO) G = G + F * kin_lo[m];
+        return G;
+    };
+    // post-processing: pairs (k, N-k), even outputs and differences D_k
+    sfor<0, R1 / 2>([&](auto Rr) QT_INL {
+        constexpr int r = Rr;
+        {
+            cx<R> y = v[r];
+            cx<R> yp = pick(lane0, v[(R1 - r) % R1], v[R1 + R1 - 1 - r]);
+            const int k = ln.ja + r * T;
+            cx<R> F = mul_ihalf(y - yp);
+            if constexpr (KIN) F = kmul(F, 2 * k);
+            buf[pad(2 * k)] = F;
+            buf[pad(2 * k + 1)] = scale(y + yp, half);
+        }
+        {
+            cx<R> y = v[R1 + r];
+            cx<R> yp = pick(lane0, v[R1 + R1 - 1 - r], v[R1 - 1 - r]);
+            const int k = ln.jb + r * T;
+            cx<R> F = mul_ihalf(y - yp);
+            if constexpr (KIN) F = kmul(F, 2 * k);
+            buf[pad(2 * k)] = F;
+            buf[pad(2 * k + 1)] = scale(y + yp, half);
+        }
+    });
+    __syncthreads();
+    // prefix sum of D_k over k = 0..N/2-1: contiguous chunks per lane
+    constexpr int CH = N / (2 * W);
+    const cx<R> d0 = buf[pad(1)];
+    cx<R> pre[CH];
+    cx<R> run = mk(R(0), R(0));
+    sfor<0, CH>([&](auto I) QT_INL {
+        const int k = ln.t * CH + I;
+        run = run + buf[pad(2 * k + 1)];
+        pre[I] = run;
+    });
+    const cx<R> off = block_exclusive_scan<W>(run, wsum) - scale(d0, half);
+    sfor<0, CH>([&](auto I) QT_INL {
+        const int k = ln.t * CH + I;
+        cx<R> F = pre[I] + off;
+        if constexpr (KIN) F = kmul(F, 2 * k + 1);
+        buf[pad(2 * k + 1)] = F;
+    });
+    __syncthreads();
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        a[Rr] = buf[pad(ln.ja + Rr * T)];
+        b[Rr] = buf[pad(ln.jb + Rr * T)];
+    });
+    __syncthreads();
+}
+
+// --------------------------------------------------------------- Philox ---
+
+struct U4 { uint64_t w[4]; };
+
+__device__ __forceinline__ U4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                            uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+        const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    U4 o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+}
+
+__device__ __forceinline__ double uniform01(uint64_t w)
+{
+    return ((double)(w >> 12) + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+// Random block of event e (0 = start, e >= 1 = e-th jump) of a trajectory.
+__device__ __forceinline__ U4 event_block(uint64_t seed, uint64_t traj_id, int64_t e)
+{
+    return philox4x64_10((uint64_t)e + 1u, traj_id, 0u, 0u, seed, 0u);
+}
+
+// --------------------------------------------------------- temperature ----
+
+// Linear interpolation in the table; `cur` is a cursor that only moves
+// forward (t grows with the step index).
+__device__ __forceinline__ double temperature_at(const double* __restrict__ tau,
+                                                 const double* __restrict__ Tt, int n, double t,
+                                                 int& cur)
+{
+    if (t <= tau[0]) return Tt[0];
+    if (t >= tau[n - 1]) return Tt[n - 1];
+    while (!(tau[cur + 1] > t)) ++cur;
+    const double w = (t - tau[cur]) / (tau[cur + 1] - tau[cur]);
+    return Tt[cur] + (Tt[cur + 1] - Tt[cur]) * w;
+}
+
+}  // namespace qt

@@ -1,0 +1,79 @@
+// qt_host.hpp -- host-side runtime shared by the C ABI entry points.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "qt_internal.h"
+
+struct qt_context {
+    int device = 0;
+    int n_cu = 0;
+    std::mutex mu;
+    struct Tables { void* tw = nullptr; void* sines = nullptr; };
+    std::map<std::pair<int, int>, Tables> tables;          // (precision, N)
+    struct Variant { int W = 0; int slots_per_cu = 0; bool tuned = false; };
+    std::map<std::pair<int, int>, Variant> plans;          // (precision, N)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    int64_t last_launches = 0;
+    std::vector<hipStream_t> aux;                          // fork/join streams
+};
+
+namespace qt {
+
+qt_status fail(qt_status s, const char* fmt, ...);
+#define QT_HIP(x)                                                                         \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) return ::qt::fail(QT_EDEVICE, "%s failed: %s", #x,          \
+                                                hipGetErrorString(e_));                   \
+    } while (0)
+
+int elem_bytes(int prec);     // bytes of one complex value of the precision
+
+// Host copy of one batch's setup (everything the device needs, in FP64).
+struct HostBatch {
+    qt_physics phys;
+    qt_batch batch;
+    int init_l = 0, init_color = 0;
+    int64_t n_steps = 0;
+    std::vector<double> tau, T;
+    double tau_start = 0, T_final = 0;
+    std::vector<double> kin;        // 2N: (2/N) exp(-i E_k dt)
+    std::vector<double> init_psi;   // 2N
+    std::vector<double> basis;      // 6N
+    double init_overlap[6] = {0, 0, 0, 0, 0, 0};
+};
+
+qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in,
+                   const qt_batch* b);
+qt_status prepare(const qt_physics* p, const qt_ttable* tt, const qt_init* in,
+                  const qt_batch* b, HostBatch* out);
+int64_t count_steps(const qt_physics& p, const qt_ttable& tt);
+double host_temperature(const double* tau, const double* T, int n, double t);
+
+qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* out);
+qt_status choose_variant(qt_context* ctx, int prec, int N, qt_context::Variant* out);
+
+// Device image of a set of groups: one allocation holding group descriptors
+// and every table they point to.  `kin` is converted to the precision.
+struct DeviceGroups {
+    void* mem = nullptr;
+    size_t bytes = 0;
+    GroupDesc* groups = nullptr;     // device
+    std::vector<GroupDesc> host;     // host copy
+};
+qt_status upload_groups(const std::vector<const HostBatch*>& hb, int prec,
+                        const std::vector<qt_results>& outs, bool with_Tn,
+                        hipStream_t s, bool async_alloc, DeviceGroups* out);
+
+// LPT order of (group, index) items: longest remaining work first.
+void build_items(const std::vector<const HostBatch*>& hb, std::vector<int32_t>* ig,
+                 std::vector<int64_t>* ii);
+
+}  // namespace qt

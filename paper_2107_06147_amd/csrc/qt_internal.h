@@ -1,0 +1,81 @@
+// qt_internal.h -- structures shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/qtraj.h"
+
+namespace qt {
+
+// Per-trajectory state between segments (and the record of the plain form).
+struct TrajState {
+    int64_t step;         // steps taken
+    int32_t l, c, n_jumps, status;
+    int32_t started, done, pad0, pad1;
+    double  r, first_r, min_gap, norm;
+};
+
+// One batch of trajectories that share physics, table and initial state.
+struct GroupDesc {
+    double  L, dr, dt, mass, alpha, kappa_hat, gamma_hat, r_max;
+    double  tau_start;
+    int32_t N, do_jumps, max_jumps, init_l, init_color, flags, n_tab, pad0;
+    int64_t n_steps, n_traj;
+    uint64_t seed, traj_id0, traj_id_stride;
+    const double* tau;
+    const double* Ttab;
+    const void*   kin;        // N complex, precision of the kernel, 2/N folded in
+    const void*   kin_lo;     // FP32 form: N complex low parts (kin - hi), else null
+    const double* init_psi;   // 2N doubles (re, im)
+    const double* basis;      // 6N doubles
+    const double* Tn;         // per-step temperature (plain form only)
+    const void*   phase;      // [(2 l + c) N + m]: exp(-i dt/2 V_static), l <= l_tab
+    int32_t l_tab, pad1;
+    double  init_overlap[6];
+    qt_results out;           // device pointers
+    void*      st_psi;        // n_traj * N complex (segmented runs), or null
+    TrajState* st;            // n_traj records (segmented runs), or null
+};
+
+struct FusedArgs {
+    const GroupDesc* groups;
+    const int32_t*   item_group;
+    const int64_t*   item_index;
+    int32_t          n_items;
+    int32_t*         queue;
+    const void*      tw;      // N complex: exp(-2 pi i m / N)
+    const void*      sines;   // N reals: sin(pi m / N)
+    int64_t          seg_steps;   // <= 0: run to the end
+};
+
+// Kernel launchers (qt_kernels.hip).  Return hipSuccess or the launch error.
+struct FusedKey { int prec; int N; int W; };
+typedef hipError_t (*fused_launcher)(const FusedArgs&, int grid, hipStream_t s);
+// Threads-per-trajectory candidates compiled for (precision, N); count returned.
+int fused_variants(int prec, int N, int* W_out, int max_out);
+fused_launcher fused_get(int prec, int N, int W);
+// Occupancy of a variant: resident workgroups per CU.
+int fused_occupancy(int prec, int N, int W);
+
+hipError_t launch_queue_reset(int32_t* q, hipStream_t s);
+
+// Plain (unfused, FP64) form: one kernel per sub-step.
+struct PlainArgs {
+    const GroupDesc* g;       // one group
+    double*    psi;           // n_traj * 2N doubles, natural order
+    TrajState* st;
+    int64_t    n_traj;
+    int32_t    N;
+    const void* tw;
+    const void* sines;
+};
+hipError_t plain_init(const PlainArgs& a, hipStream_t s);
+hipError_t plain_space(const PlainArgs& a, int64_t n, hipStream_t s);
+hipError_t plain_dst(const PlainArgs& a, hipStream_t s);
+hipError_t plain_kinetic(const PlainArgs& a, hipStream_t s);
+hipError_t plain_norm_jump(const PlainArgs& a, int64_t n, hipStream_t s);
+hipError_t plain_finalize(const PlainArgs& a, hipStream_t s);
+bool plain_supported(int N);
+
+}  // namespace qt

@@ -1,0 +1,315 @@
+"""ctypes binding of libqtraj.so (the C ABI of include/qtraj.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  The functions keep the C names (qt_context_create, qt_run,
+...); `run()` and `run_many()` additionally turn the config dicts of
+`paper_2107_06147_amd.workloads` into the C structs and allocate the output
+tensors on the GPU with torch (torch provides device memory and streams).
+
+If libqtraj.so has not been built this module raises on first use; there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqtraj.so")
+
+QT_OK, QT_EINVAL, QT_ENOMEM, QT_EDEVICE, QT_EBUSY, QT_ETIMEOUT, QT_ECANCELED, QT_ENOTFOUND = range(8)
+QT_FP64, QT_FP32_BULK = 0, 1
+QT_FORM_FUSED, QT_FORM_PLAIN = 0, 1
+QT_INIT_COULOMB, QT_INIT_GAUSSIAN, QT_INIT_ARRAY = 0, 1, 2
+QT_SINGLET, QT_OCTET = 0, 1
+QT_TRAJ_OK, QT_TRAJ_RMAX, QT_TRAJ_MAXJUMPS = 0, 1, 2
+QT_FLAG_KINETIC_OFF = 1
+
+_D = C.POINTER(C.c_double)
+_I32 = C.POINTER(C.c_int32)
+_I64 = C.POINTER(C.c_int64)
+
+
+class qt_physics(C.Structure):
+    _fields_ = [("N", C.c_int32), ("L", C.c_double), ("dt", C.c_double), ("mass", C.c_double),
+                ("alpha_s", C.c_double), ("kappa_hat", C.c_double), ("gamma_hat", C.c_double),
+                ("deriv_type", C.c_int32), ("do_jumps", C.c_int32), ("max_jumps", C.c_int32),
+                ("r_max", C.c_double), ("flags", C.c_int32)]
+
+
+class qt_ttable(C.Structure):
+    _fields_ = [("tau", _D), ("T", _D), ("n", C.c_int32), ("tau_start", C.c_double),
+                ("T_final", C.c_double), ("max_steps", C.c_int64)]
+
+
+class qt_init(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("l", C.c_int32), ("color", C.c_int32),
+                ("width", C.c_double), ("u_re", _D), ("u_im", _D)]
+
+
+class qt_batch(C.Structure):
+    _fields_ = [("n_traj", C.c_int64), ("seed", C.c_uint64), ("traj_id0", C.c_uint64),
+                ("traj_id_stride", C.c_uint64), ("precision", C.c_int32), ("form", C.c_int32)]
+
+
+class qt_results(C.Structure):
+    _fields_ = [("norm", _D), ("first_r", _D), ("overlap", _D), ("survival", _D),
+                ("mean_r", _D), ("l", _I32), ("color", _I32), ("n_jumps", _I32),
+                ("status", _I32), ("steps_done", _I64), ("min_gap", _D), ("psi", _D)]
+
+
+class qt_server_cfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("segment_steps", C.c_int64),
+                ("precision", C.c_int32)]
+
+
+class qt_stats(C.Structure):
+    _fields_ = [("p50_latency_s", C.c_double), ("p99_latency_s", C.c_double),
+                ("mean_latency_s", C.c_double), ("traj_steps_per_s", C.c_double),
+                ("completed", C.c_int64), ("admitted", C.c_int64), ("queued", C.c_int64),
+                ("running", C.c_int64), ("traj_steps", C.c_int64), ("hbm_in_use", C.c_size_t)]
+
+
+# every symbol the header declares, with (restype, argtypes)
+_VP = C.c_void_p
+_SIGS = {
+    "qt_context_create": (C.c_int, [C.c_int, C.POINTER(_VP)]),
+    "qt_context_destroy": (C.c_int, [_VP]),
+    "qt_run": (C.c_int, [_VP, C.POINTER(qt_physics), C.POINTER(qt_ttable), C.POINTER(qt_init),
+                         C.POINTER(qt_batch), C.POINTER(qt_results), _VP]),
+    "qt_run_many": (C.c_int, [_VP, C.c_int32, C.POINTER(qt_physics), C.POINTER(qt_ttable),
+                              C.POINTER(qt_init), C.POINTER(qt_batch), C.POINTER(qt_results), _VP]),
+    "qt_job_create": (C.c_int, [_VP, C.POINTER(qt_physics), C.POINTER(qt_ttable),
+                                C.POINTER(qt_init), C.POINTER(qt_batch), C.c_int64,
+                                C.POINTER(_VP)]),
+    "qt_job_advance": (C.c_int, [_VP, C.c_int64, _VP]),
+    "qt_job_done": (C.c_int, [_VP, _I32]),
+    "qt_job_state_bytes": (C.c_int, [_VP, C.POINTER(C.c_size_t)]),
+    "qt_job_save": (C.c_int, [_VP, _VP, _VP]),
+    "qt_job_load": (C.c_int, [_VP, _VP, _VP]),
+    "qt_job_results": (C.c_int, [_VP, C.POINTER(qt_results), _VP]),
+    "qt_job_destroy": (C.c_int, [_VP]),
+    "qt_server_create": (C.c_int, [_VP, C.POINTER(qt_server_cfg), C.POINTER(_VP)]),
+    "qt_submit": (C.c_int, [_VP, C.POINTER(qt_physics), C.POINTER(qt_ttable), C.POINTER(qt_init),
+                            C.POINTER(qt_batch), C.POINTER(C.c_uint64)]),
+    "qt_poll": (C.c_int, [_VP, C.c_uint64, _I32]),
+    "qt_wait": (C.c_int, [_VP, C.c_uint64, C.POINTER(qt_results), C.c_double]),
+    "qt_cancel": (C.c_int, [_VP, C.c_uint64]),
+    "qt_server_stats": (C.c_int, [_VP, C.POINTER(qt_stats)]),
+    "qt_server_destroy": (C.c_int, [_VP]),
+    "qt_last_kernel_ms": (C.c_int, [_VP, _D, _I64]),
+    "qt_plan": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _I32, _I32]),
+    "qt_last_error": (C.c_char_p, []),
+    "qt_version": (C.c_char_p, []),
+}
+SYMBOLS = tuple(_SIGS)
+
+_lib = None
+
+
+def lib():
+    """Load libqtraj.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libqtraj.so is missing: build it with __graft_entry__.build() "
+                               "(hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class QtError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib().qt_last_error().decode(errors="replace")
+        super().__init__("%s failed (status %d): %s" % (where, status, msg))
+        self.status = status
+
+
+def check(status, where):
+    if status != QT_OK:
+        raise QtError(status, where)
+
+
+# ------------------------------------------------------------ marshalling --
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def physics(cfg):
+    return qt_physics(int(cfg["N"]), float(cfg["L"]), float(cfg["dt"]), float(cfg["mass"]),
+                      float(cfg["alpha_s"]), float(cfg["kappa_hat"]), float(cfg["gamma_hat"]),
+                      int(cfg.get("deriv_type", 0)), int(cfg.get("do_jumps", 1)),
+                      int(cfg.get("max_jumps", -1)), float(cfg.get("r_max", 1.0)),
+                      int(cfg.get("flags", 0)))
+
+
+def ttable(cfg, keep):
+    tau = np.ascontiguousarray(cfg["tau"], dtype=np.float64)
+    T = np.ascontiguousarray(cfg["T"], dtype=np.float64)
+    keep += [tau, T]
+    return qt_ttable(_dp(tau), _dp(T), len(tau), float(cfg["tau_start"]),
+                     float(cfg.get("T_final", 0.0)), int(cfg.get("max_steps", 2**62)))
+
+
+def init(cfg, keep):
+    kind = int(cfg.get("init_kind", QT_INIT_COULOMB))
+    u_re = u_im = None
+    if kind == QT_INIT_ARRAY:
+        u = np.asarray(cfg["u0"])
+        u_re = np.ascontiguousarray(u.real, dtype=np.float64)
+        u_im = np.ascontiguousarray(u.imag, dtype=np.float64)
+        keep += [u_re, u_im]
+    return qt_init(kind, int(cfg.get("init_n", 1)), int(cfg.get("init_l", 0)),
+                   int(cfg.get("init_color", QT_SINGLET)), float(cfg.get("init_width", 0.0)),
+                   _dp(u_re), _dp(u_im))
+
+
+def batch(cfg, precision, form=QT_FORM_FUSED, n_traj=None, traj_id0=None):
+    return qt_batch(int(cfg["n_traj"] if n_traj is None else n_traj), int(cfg.get("seed", 1)),
+                    int(cfg.get("traj_id0", 0) if traj_id0 is None else traj_id0),
+                    int(cfg.get("traj_id_stride", 1)), int(precision), int(form))
+
+
+def alloc_results(n, N, want_psi, device="cuda"):
+    """Output tensors on the GPU (torch) and the qt_results of their pointers."""
+    import torch
+    f64 = dict(dtype=torch.float64, device=device)
+    out = {
+        "norm": torch.zeros(n, **f64), "first_r": torch.zeros(n, **f64),
+        "overlap": torch.zeros(n, 6, **f64), "survival": torch.zeros(n, 6, **f64),
+        "mean_r": torch.zeros(n, **f64),
+        "l": torch.zeros(n, dtype=torch.int32, device=device),
+        "color": torch.zeros(n, dtype=torch.int32, device=device),
+        "n_jumps": torch.zeros(n, dtype=torch.int32, device=device),
+        "status": torch.zeros(n, dtype=torch.int32, device=device),
+        "steps_done": torch.zeros(n, dtype=torch.int64, device=device),
+        "min_gap": torch.zeros(n, **f64),
+    }
+    if want_psi:
+        out["psi"] = torch.zeros(n, N, 2, **f64)
+    return out, results_struct(out)
+
+
+def results_struct(out):
+    def p(name, typ):
+        t = out.get(name)
+        return C.cast(C.c_void_p(t.data_ptr()), typ) if t is not None else None
+    return qt_results(p("norm", _D), p("first_r", _D), p("overlap", _D), p("survival", _D),
+                      p("mean_r", _D), p("l", _I32), p("color", _I32), p("n_jumps", _I32),
+                      p("status", _I32), p("steps_done", _I64), p("min_gap", _D), p("psi", _D))
+
+
+def host_results(n, N, want_psi):
+    """Output arrays in host memory (numpy) and their qt_results."""
+    out = {
+        "norm": np.zeros(n), "first_r": np.zeros(n), "overlap": np.zeros((n, 6)),
+        "survival": np.zeros((n, 6)), "mean_r": np.zeros(n),
+        "l": np.zeros(n, np.int32), "color": np.zeros(n, np.int32),
+        "n_jumps": np.zeros(n, np.int32), "status": np.zeros(n, np.int32),
+        "steps_done": np.zeros(n, np.int64), "min_gap": np.zeros(n),
+    }
+    if want_psi:
+        out["psi"] = np.zeros((n, N, 2))
+    r = qt_results(*[(_dp(out[k]) if out[k].dtype == np.float64 else
+                      out[k].ctypes.data_as(_I32 if out[k].dtype == np.int32 else _I64))
+                     for k in ("norm", "first_r", "overlap", "survival", "mean_r", "l", "color",
+                               "n_jumps", "status", "steps_done", "min_gap")],
+                   _dp(out.get("psi")))
+    return out, r
+
+
+def to_numpy(out):
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    if "psi" in res:
+        res["psi"] = res["psi"][..., 0] + 1j * res["psi"][..., 1]
+    return res
+
+
+# ---------------------------------------------------------------- context --
+
+class Context:
+    """Owns a qt_context on one HIP device."""
+
+    def __init__(self, device=0):
+        h = _VP()
+        check(lib().qt_context_create(int(device), C.byref(h)), "qt_context_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().qt_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_kernel_ms(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        check(lib().qt_last_kernel_ms(self.h, C.byref(ms), C.byref(n)), "qt_last_kernel_ms")
+        return ms.value, n.value
+
+    def plan(self, N, precision, tune=False):
+        w = C.c_int32()
+        s = C.c_int32()
+        check(lib().qt_plan(self.h, int(N), int(precision), int(bool(tune)), C.byref(w),
+                            C.byref(s)), "qt_plan")
+        return w.value, s.value
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def run(ctx, cfg, precision=QT_FP64, form=QT_FORM_FUSED, want_psi=False, n_traj=None,
+        traj_id0=None, stream=None, out=None):
+    """qt_run on a config dict; returns the dict of output tensors."""
+    keep = []
+    n = int(cfg["n_traj"] if n_traj is None else n_traj)
+    if out is None:
+        out, res = alloc_results(n, int(cfg["N"]), want_psi)
+    else:
+        res = results_struct(out)
+    p = physics(cfg)
+    tt = ttable(cfg, keep)
+    ini = init(cfg, keep)
+    b = batch(cfg, precision, form, n, traj_id0)
+    check(lib().qt_run(ctx.h, C.byref(p), C.byref(tt), C.byref(ini), C.byref(b), C.byref(res),
+                       _stream_handle(stream)), "qt_run")
+    return out
+
+
+def run_many(ctx, cfgs, precision=QT_FP32_BULK, want_psi=False, stream=None):
+    """qt_run_many over a list of config dicts; returns one output dict each."""
+    keep = []
+    k = len(cfgs)
+    P = (qt_physics * k)()
+    TT = (qt_ttable * k)()
+    IN = (qt_init * k)()
+    B = (qt_batch * k)()
+    RS = (qt_results * k)()
+    outs = []
+    for i, cfg in enumerate(cfgs):
+        o, r = alloc_results(int(cfg["n_traj"]), int(cfg["N"]), want_psi)
+        outs.append(o)
+        P[i] = physics(cfg)
+        TT[i] = ttable(cfg, keep)
+        IN[i] = init(cfg, keep)
+        B[i] = batch(cfg, precision, QT_FORM_FUSED)
+        RS[i] = r
+    check(lib().qt_run_many(ctx.h, k, P, TT, IN, B, RS, _stream_handle(stream)), "qt_run_many")
+    return outs

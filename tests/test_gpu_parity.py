@@ -1,0 +1,146 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle,
+element by element on the same seeded inputs.  Marked `gpu`."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_06147_amd import qtraj as qt
+from paper_2107_06147_amd import workloads as W
+from tests.gpu_parity import FP32_DELTA, FP64_DELTA, compare, gpu_run
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = qt.QT_FP64, qt.QT_FP32_BULK
+FUSED, PLAIN = qt.QT_FORM_FUSED, qt.QT_FORM_PLAIN
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = qt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c1_ref():
+    return oracle.run(W.c1_parity(), want_psi=True)
+
+
+# ---------------------------------------------------- C1: the parity config
+
+@pytest.mark.parametrize("prec,form", [(F64, FUSED), (F64, PLAIN), (F32, FUSED)])
+def test_c1_all_trajectories(ctx, c1_ref, prec, form):
+    """16 trajectories, N=512, 1000 steps, Coulomb 1S, kappa_hat=4: every
+    trajectory, every output."""
+    out = gpu_run(ctx, W.c1_parity(), prec, form)
+    st = compare(c1_ref, out, prec, label="c1 prec=%d form=%d" % (prec, form))
+    print("c1", prec, form, st)
+    assert c1_ref["n_jumps"].sum() > 0          # the case exercises jumps
+    assert st["near"] <= st["n"] // 2
+
+
+# ---------------------------------------------------- edge and special cases
+
+def _edge_cases():
+    bj_tau, bj_T = W.bjorken_table(0.425, 0.6, 0.25, 500)
+    bj = dict(tau=bj_tau, T=bj_T, tau_start=float(bj_tau[0]), T_final=0.25, max_steps=300)
+    small = dict(N=256, L=20.0, dt=0.001, kappa_hat=20.0, seed=9)
+    return {
+        "ragged_3": W.base(n_traj=3, **small, **W.constant_T(0.5, 300)),
+        "octet_gauss_l2": W.base(n_traj=6, init_kind=W.INIT_GAUSSIAN, init_l=2, init_color=W.OCTET,
+                                 init_width=1.0, **small, **W.constant_T(0.5, 300)),
+        "deriv1_gamma_bjorken": W.base(n_traj=6, deriv_type=1, gamma_hat=-2.0,
+                                       **dict(small, kappa_hat=4.0), **bj),
+        "kinetic_off": W.base(n_traj=4, flags=qt.QT_FLAG_KINETIC_OFF, **small,
+                              **W.constant_T(0.5, 200)),
+        "rmax": W.base(n_traj=12, r_max=0.4, **small, **W.constant_T(0.5, 200)),
+        "maxjumps_1": W.base(n_traj=12, max_jumps=1, **small, **W.constant_T(0.5, 400)),
+        "no_jumps": W.base(n_traj=2, do_jumps=0, **small, **W.constant_T(0.5, 300)),
+        "zero_steps": W.base(n_traj=5, **small, **W.constant_T(0.5, 0)),
+        "stride_ids": W.base(n_traj=7, traj_id0=5, traj_id_stride=3, **small,
+                             **W.constant_T(0.5, 200)),
+        "coulomb_2p": W.base(n_traj=5, init_kind=W.INIT_COULOMB, init_n=3, init_l=1, **small,
+                             **W.constant_T(0.5, 200)),
+    }
+
+
+EDGE = _edge_cases()
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_edge_cases(ctx, name, prec):
+    cfg = EDGE[name]
+    ref = oracle.run(cfg, want_psi=True)
+    out = gpu_run(ctx, cfg, prec)
+    st = compare(ref, out, prec, label=name)
+    print(name, prec, st)
+    if name == "rmax":
+        assert (out["status"] == qt.QT_TRAJ_RMAX).any() and (out["status"] == qt.QT_TRAJ_OK).any()
+    if name == "maxjumps_1":
+        assert (out["status"] == qt.QT_TRAJ_MAXJUMPS).any()
+    if name == "zero_steps":
+        assert np.all(out["steps_done"] == 0)
+
+
+@pytest.mark.parametrize("name", ["ragged_3", "deriv1_gamma_bjorken", "rmax", "maxjumps_1"])
+def test_edge_cases_plain(ctx, name):
+    cfg = EDGE[name]
+    ref = oracle.run(cfg, want_psi=True)
+    out = gpu_run(ctx, cfg, F64, PLAIN)
+    compare(ref, out, F64, label="plain " + name)
+
+
+def test_empty_batch(ctx):
+    cfg = W.base(N=256, n_traj=0, **W.constant_T(0.5, 10))
+    out = gpu_run(ctx, cfg, F64)
+    assert len(out["norm"]) == 0
+    out = gpu_run(ctx, cfg, F64, PLAIN)
+    assert len(out["norm"]) == 0
+
+
+# ----------------------------------------------------------- every grid size
+
+@pytest.mark.parametrize("N", [256, 512, 1024, 2048, 4096, 8192])
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_grid_sizes(ctx, N, prec):
+    steps = {256: 200, 512: 150, 1024: 100, 2048: 60, 4096: 30, 8192: 12}[N]
+    cfg = W.base(N=N, L=N * 5.0 / 256.0, dt=0.001, kappa_hat=50.0, n_traj=2, seed=13,
+                 init_kind=W.INIT_GAUSSIAN, init_width=1.0, init_l=1, **W.constant_T(0.5, steps))
+    ref = oracle.run(cfg, want_psi=True)
+    out = gpu_run(ctx, cfg, prec)
+    print(N, prec, compare(ref, out, prec, label="N=%d" % N))
+
+
+# ------------------------------------- C2 at full size, sampled trajectories
+
+C2_SAMPLE = [0, 1, 2047, 4095]
+
+
+@pytest.mark.parametrize("prec,form", [(F64, FUSED), (F32, FUSED), (F64, PLAIN)])
+def test_c2_full_batch_sampled(ctx, prec, form):
+    """4096 trajectories at N=2048 in the benchmark's launch configuration,
+    truncated to 120 steps; sampled trajectories against the oracle, every
+    trajectory against the invariants."""
+    cfg = W.c2_headline(kappa_hat=4.0, gamma_hat=-2.0)
+    cfg["max_steps"] = 120
+    out = gpu_run(ctx, cfg, prec, form, want_psi=False)
+    assert np.all(out["steps_done"] == 120) or np.all(out["status"] != qt.QT_TRAJ_OK)
+    assert np.all((out["norm"] > 0) & (out["norm"] <= 1.0 + 1e-6))
+    assert np.all((out["l"] - cfg["init_l"] - out["n_jumps"]) % 2 == 0)   # each jump: l +- 1
+    assert np.all(out["color"][out["n_jumps"] == 0] == W.SINGLET)
+    assert np.all(out["color"][out["n_jumps"] == 1] == W.OCTET)
+    for tid in C2_SAMPLE:
+        ref = oracle.run(cfg, n_traj=1, traj_id0=tid)
+        one = {k: v[tid:tid + 1] for k, v in out.items()}
+        compare(ref, one, prec, check_psi=False, label="c2 id %d" % tid)
+
+
+def test_determinism(ctx):
+    cfg = W.c1_parity()
+    a = gpu_run(ctx, cfg, F32)
+    b = gpu_run(ctx, cfg, F32)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
