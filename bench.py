@@ -1,0 +1,234 @@
+"""Benchmark: trajectory-steps/s of the quantum-trajectory hot path at N=2048.
+
+Workload (one "step" of this benchmark = one full batch): 4096 trajectories,
+N=2048, L=40 GeV^-1, dt=0.001 GeV^-1, Bjorken cooling 0.425 GeV at 0.6 fm/c
+down to 0.25 GeV (500-point table, 11,898 time steps per trajectory),
+Gaussian l=0 singlet of width 0.2 fm, jumps on; the timed steps cycle
+through (kappa_hat, gamma_hat) in {1,4} x {0,-2}.  Inputs are synthetic and
+generated in HBM-resident form before timing (the tables are uploaded inside
+qt_run, which is part of the timed region).
+
+value      FP32-bulk fused form (FP32 wave function and transforms, FP64 norm
+           and threshold), whole-job trajectory-steps/s.
+extra      FP64 plain (unfused) and FP64 fused throughput on the same
+           workload, the FP32-bulk speedup over the plain FP64 form, and
+           p50/p99 request latency of a shortened served stream when the
+           server is available.
+roofline   the fused kernel, algorithmic flops per trajectory-step
+           F(N) = 10 N log2 N + 29 N (two complex DSTs at 5 N log2 N, three
+           complex multiplies, norm and kernel arithmetic), divided by its
+           average launch duration measured with HIP events on the stream it
+           runs on, against the FP32 vector peak.
+cpu_baseline  the FP64 oracle on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12       # MI355X FP32 vector, FLOP/s
+PEAK_FP64 = 78.6e12
+
+
+def flops_per_traj_step(N):
+    return 10.0 * N * math.log2(N) + 29.0 * N
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2107_06147_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path)).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 plain leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
+    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--profile", choices=["fp32", "fp64", "plain"], default=None,
+                    help="profiling mode: one short run of the batch (--profile-steps time "
+                         "steps) in the given form, then a 256 MiB device copy that "
+                         "calibrates HBM byte counters; prints no JSON")
+    ap.add_argument("--profile-steps", type=int, default=400)
+    return ap.parse_args()
+
+
+def profile_mode(args):
+    import torch
+
+    from paper_2107_06147_amd import qtraj as qt
+    from paper_2107_06147_amd import workloads as W
+    torch.cuda.set_device(0)
+    ctx = qt.Context(0)
+    prec = qt.QT_FP64 if args.profile in ("fp64", "plain") else qt.QT_FP32_BULK
+    form = qt.QT_FORM_PLAIN if args.profile == "plain" else qt.QT_FORM_FUSED
+    if form == qt.QT_FORM_FUSED:
+        ctx.plan(2048, prec, tune=True)
+    cfg = W.c2_headline(4.0, 0.0)
+    cfg["max_steps"] = args.profile_steps
+    out, _ = qt.alloc_results(cfg["n_traj"], 2048, False)
+    qt.run(ctx, cfg, precision=prec, form=form, out=out)
+    torch.cuda.synchronize()
+    ms, launches = ctx.last_kernel_ms()
+    tps = int(out["steps_done"].sum().item())
+    print("profile %s: %d trajectory-steps, %.3f ms over %d launches" % (args.profile, tps, ms, launches))
+    src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copy: 268435456 bytes read and written")
+    ctx.close()
+
+
+def main():
+    args = parse()
+    if args.profile:
+        profile_mode(args)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (trajectories are independent; "
+              "a multi-GPU run would shard trajectory ids, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2107_06147_amd import qtraj as qt
+    from paper_2107_06147_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    ctx = qt.Context(0)
+    N = 2048
+    runs = [W.c2_headline(k, g) for (k, g) in W.C2_RUNS]
+    n_traj = runs[0]["n_traj"]
+
+    w32, s32 = ctx.plan(N, qt.QT_FP32_BULK, tune=True)
+    w64, s64 = ctx.plan(N, qt.QT_FP64, tune=True)
+
+    out32, _ = qt.alloc_results(n_traj, N, False)
+    # trajectory-steps of one batch, as the library reports them
+    qt.run(ctx, runs[0], precision=qt.QT_FP32_BULK, out=out32)
+    torch.cuda.synchronize()
+    tps_per_run = int(out32["steps_done"].sum().item())
+    n_steps = int(out32["steps_done"].max().item())
+
+    def timed_runs(precision, form, count, out, first=0):
+        kernel_ms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(count):
+            qt.run(ctx, runs[(first + i) % len(runs)], precision=precision, form=form, out=out)
+            ms, _ = ctx.last_kernel_ms()
+            kernel_ms.append(ms)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, kernel_ms
+
+    # warmup, then the timed FP32-bulk steps
+    timed_runs(qt.QT_FP32_BULK, qt.QT_FORM_FUSED, args.warmup, out32)
+    wall, kms = timed_runs(qt.QT_FP32_BULK, qt.QT_FORM_FUSED, args.steps, out32, first=args.warmup)
+    value = tps_per_run * args.steps / wall
+    kernel_s = sum(kms) / 1e3 / len(kms)
+    achieved = tps_per_run * flops_per_traj_step(N) / kernel_s
+
+    # FP64 fused and plain on one run each (kappa_hat=4, gamma_hat=0)
+    extra = {}
+    wall64, k64 = timed_runs(qt.QT_FP64, qt.QT_FORM_FUSED, 1, out32, first=2)
+    extra["fp64_fused_traj_steps_per_s"] = tps_per_run / wall64
+    extra["fp64_fused_kernel_ms"] = k64[0]
+    if not args.no_plain:
+        wallp, kp = timed_runs(qt.QT_FP64, qt.QT_FORM_PLAIN, 1, out32, first=2)
+        extra["fp64_plain_traj_steps_per_s"] = tps_per_run / wallp
+        extra["fp64_plain_kernel_ms"] = kp[0]
+        extra["speedup_fp32_bulk_over_fp64_plain"] = value / extra["fp64_plain_traj_steps_per_s"]
+    extra["speedup_fp32_bulk_over_fp64_fused"] = value / extra["fp64_fused_traj_steps_per_s"]
+    extra["plan"] = {"fp32_threads_per_traj": w32, "fp32_traj_per_cu": s32,
+                     "fp64_threads_per_traj": w64, "fp64_traj_per_cu": s64}
+
+    if not args.no_serve:
+        try:
+            from paper_2107_06147_amd import serve
+            extra["serve"] = serve.bench_stream(ctx, duration_s=6.0)
+        except (ImportError, AttributeError, qt.QtError) as e:
+            extra["serve"] = {"skipped": str(e)}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        sample = dict(runs[2])
+        sample["max_steps"] = args.cpu_steps
+        n_sample = 16
+        t0 = time.perf_counter()
+        oracle.run(sample, n_traj=n_sample, n_threads=cores)
+        dt = time.perf_counter() - t0
+        cpu = {"value": n_sample * args.cpu_steps / dt, "unit": "trajectory-steps/s",
+               "cores": cores, "kind": "oracle",
+               "sample": "16 trajectories x %d steps of the same N=2048 batch "
+                         "(kappa_hat=4, gamma_hat=0), FP64 naive DST" % args.cpu_steps}
+
+    # a 256 MiB device copy after the timed region: HBM byte counters of
+    # this plain copy calibrate the FETCH_SIZE/WRITE_SIZE of the kernels
+    src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    torch.empty_like(src).copy_(src)
+    torch.cuda.synchronize()
+    del src
+
+    line = {
+        "metric": "trajectory-steps/s at N=2048, FP32-bulk vs FP64 plain; p50/p99 request latency",
+        "value": value,
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "4096 trajectories, N=2048, L=40, dt=0.001, Bjorken 0.425->0.25 GeV "
+                               "(11898 steps), Gaussian l=0 singlet 0.2 fm, jumps on, "
+                               "kappa_hat in {1,4} x gamma_hat in {0,-2}",
+                   "trajectories": n_traj, "grid_points": N, "time_steps": n_steps,
+                   "form": "fused persistent, FP32 bulk + FP64 norm/threshold"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": measured_traffic("fused_kernel<float, 2048"),
+                     "kernel_ms": kernel_s * 1e3,
+                     "flops_per_traj_step": flops_per_traj_step(N)},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

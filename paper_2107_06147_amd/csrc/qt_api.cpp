@@ -627,6 +627,55 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
     return QT_OK;
 }
 
+// Autotuner: times every compiled variant (threads per trajectory, hence
+// radix plan and registers per lane) on a synthetic batch that fills the
+// device, and keeps the fastest for (precision, N).
+qt_status tune_variant(qt_context* ctx, int prec, int N, qt_context::Variant* out)
+{
+    int Ws[16];
+    const int nv = fused_variants(prec, N, Ws, 16);
+    const double tau[2] = {0.0, 1e9}, T[2] = {0.4, 0.4};
+    qt_physics p{};
+    p.N = N; p.L = N * 5.0 / 256.0; p.dt = 0.001; p.mass = 4.65; p.alpha_s = 0.3;
+    p.kappa_hat = 4.0; p.gamma_hat = 0.0; p.deriv_type = 0; p.do_jumps = 1; p.max_jumps = -1;
+    p.r_max = 1.0; p.flags = 0;
+    qt_ttable tt{tau, T, 2, 0.0, 0.0, 120};
+    qt_init in{QT_INIT_GAUSSIAN, 1, 0, QT_SINGLET, 1.0, nullptr, nullptr};
+    qt_batch b{};
+    b.n_traj = (int64_t)ctx->n_cu * 8; b.seed = 12345; b.traj_id0 = 0; b.traj_id_stride = 1;
+    b.precision = prec; b.form = QT_FORM_FUSED;
+    HostBatch hb;
+    qt_status st = prepare(&p, &tt, &in, &b, &hb);
+    if (st != QT_OK) return st;
+    std::vector<const HostBatch*> v{&hb};
+    std::vector<qt_results> outs(1);
+    std::memset(&outs[0], 0, sizeof(qt_results));
+    auto key = std::make_pair(prec, N);
+    double best_ms = 1e300;
+    qt_context::Variant best{};
+    for (int i = 0; i < nv; ++i) {
+        qt_context::Variant cand;
+        cand.W = Ws[i];
+        cand.slots_per_cu = fused_occupancy(prec, N, Ws[i]);
+        if (cand.slots_per_cu <= 0) continue;
+        ctx->plans[key] = cand;
+        double ms = 0;
+        for (int rep = 0; rep < 2; ++rep) {   // first run warms up
+            if ((st = run_fused_groups(ctx, v, outs, prec, nullptr)) != QT_OK) return st;
+            QT_HIP(hipEventSynchronize(ctx->ev1));
+            float f = 0.f;
+            QT_HIP(hipEventElapsedTime(&f, ctx->ev0, ctx->ev1));
+            ms = f;
+        }
+        if (ms < best_ms) { best_ms = ms; best = cand; }
+    }
+    if (best.W == 0) return fail(QT_EDEVICE, "no runnable variant for N=%d", N);
+    best.tuned = true;
+    ctx->plans[key] = best;
+    *out = best;
+    return QT_OK;
+}
+
 qt_status run_plain(qt_context* ctx, const HostBatch& hb, const qt_results& out, hipStream_t s)
 {
     const int N = hb.phys.N;
@@ -730,7 +779,9 @@ qt_status qt_plan(qt_context* ctx, int32_t N, int32_t precision, int32_t tune,
     qt_context::Variant v;
     qt_status st = choose_variant(ctx, precision, N, &v);
     if (st != QT_OK) return st;
-    (void)tune;
+    if (tune && !v.tuned) {
+        if ((st = tune_variant(ctx, precision, N, &v)) != QT_OK) return st;
+    }
     if (threads_per_traj) *threads_per_traj = v.W;
     if (traj_per_cu) *traj_per_cu = v.slots_per_cu;
     return QT_OK;
