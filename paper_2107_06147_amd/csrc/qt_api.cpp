@@ -333,7 +333,27 @@ static void phase_table(const HostBatch& h, bool f32, char* dst)
         }
 }
 
-qt_status upload_groups(const std::vector<const HostBatch*>& hb, int prec,
+qt_status ensure_phase(qt_context* ctx, const HostBatch& h, int prec, const void** out)
+{
+    std::vector<double> key{(double)prec, (double)h.phys.N, h.phys.L, h.phys.mass, h.phys.alpha_s,
+                            h.phys.dt};
+    auto it = ctx->phase.find(key);
+    if (it != ctx->phase.end()) {
+        *out = it->second;
+        return QT_OK;
+    }
+    const size_t bytes = (size_t)2 * (kLTab + 1) * h.phys.N * elem_bytes(prec);
+    std::vector<char> tab(bytes);
+    phase_table(h, prec == QT_FP32_BULK, tab.data());
+    void* d = nullptr;
+    QT_HIP(hipMalloc(&d, bytes));
+    QT_HIP(hipMemcpy(d, tab.data(), bytes, hipMemcpyHostToDevice));
+    ctx->phase[key] = d;
+    *out = d;
+    return QT_OK;
+}
+
+qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb, int prec,
                         const std::vector<qt_results>& outs, bool with_Tn, hipStream_t s,
                         bool async_alloc, DeviceGroups* dg)
 {
@@ -353,25 +373,12 @@ qt_status upload_groups(const std::vector<const HostBatch*>& hb, int prec,
         o[g].Tn = off;
         if (with_Tn) off = align_up(off + (size_t)std::max<int64_t>(h.n_steps, 1) * 8);
     }
-    // static phase tables, one per distinct (N, L, mass, alpha_s, dt)
-    std::vector<size_t> phase_off(ng, 0);
-    std::vector<std::pair<std::vector<double>, size_t>> keys;
-    std::vector<size_t> key_first;
-    if (!with_Tn) {
+    std::vector<const void*> phase(ng, nullptr);
+    if (!with_Tn)
         for (size_t g = 0; g < ng; ++g) {
-            const HostBatch& h = *hb[g];
-            std::vector<double> k{(double)h.phys.N, h.phys.L, h.phys.mass, h.phys.alpha_s, h.phys.dt};
-            size_t found = keys.size();
-            for (size_t q = 0; q < keys.size(); ++q)
-                if (keys[q].first == k) { found = q; break; }
-            if (found == keys.size()) {
-                keys.push_back({k, off});
-                key_first.push_back(g);
-                off = align_up(off + (size_t)2 * (kLTab + 1) * h.phys.N * elem_bytes(prec));
-            }
-            phase_off[g] = keys[found].second;
+            qt_status st = ensure_phase(ctx, *hb[g], prec, &phase[g]);
+            if (st != QT_OK) return st;
         }
-    }
     dg->bytes = off;
     if (async_alloc) {
         QT_HIP(hipMallocAsync(&dg->mem, off, s));
@@ -401,7 +408,7 @@ qt_status upload_groups(const std::vector<const HostBatch*>& hb, int prec,
         d.init_psi = reinterpret_cast<const double*>(base + o[g].init);
         d.basis = reinterpret_cast<const double*>(base + o[g].basis);
         d.Tn = with_Tn ? reinterpret_cast<const double*>(base + o[g].Tn) : nullptr;
-        d.phase = with_Tn ? nullptr : base + phase_off[g];
+        d.phase = phase[g];
         d.l_tab = kLTab;
         for (int q = 0; q < 6; ++q) d.init_overlap[q] = h.init_overlap[q];
         d.out = outs[g];
@@ -429,7 +436,6 @@ qt_status upload_groups(const std::vector<const HostBatch*>& hb, int prec,
                                          h.tau_start + (double)n * h.phys.dt);
         }
     }
-    for (size_t q = 0; q < keys.size(); ++q) phase_table(*hb[key_first[q]], f32, &blob[keys[q].second]);
     std::memcpy(blob.data(), dg->host.data(), ng * sizeof(GroupDesc));
     dg->groups = reinterpret_cast<GroupDesc*>(base);
     QT_HIP(hipMemcpyAsync(dg->mem, blob.data(), off, hipMemcpyHostToDevice, s));
@@ -527,6 +533,7 @@ qt_status qt_context_destroy(qt_context* ctx)
         hipFree(kv.second.tw);
         hipFree(kv.second.sines);
     }
+    for (auto& kv : ctx->phase) hipFree(kv.second);
     for (hipStream_t s : ctx->aux) hipStreamDestroy(s);
     hipEventDestroy(ctx->ev0);
     hipEventDestroy(ctx->ev1);
@@ -564,7 +571,7 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
     for (const HostBatch* h : hb)
         if (std::find(Ns.begin(), Ns.end(), h->phys.N) == Ns.end()) Ns.push_back(h->phys.N);
     DeviceGroups dg;
-    qt_status st = upload_groups(hb, prec, outs, false, s, true, &dg);
+    qt_status st = upload_groups(ctx, hb, prec, outs, false, s, true, &dg);
     if (st != QT_OK) return st;
     std::vector<int32_t> ig;
     std::vector<int64_t> ii;
@@ -684,7 +691,7 @@ qt_status run_plain(qt_context* ctx, const HostBatch& hb, const qt_results& out,
     std::vector<const HostBatch*> v{&hb};
     std::vector<qt_results> outs{out};
     DeviceGroups dg;
-    qt_status st = upload_groups(v, QT_FP64, outs, true, s, true, &dg);
+    qt_status st = upload_groups(ctx, v, QT_FP64, outs, true, s, true, &dg);
     if (st != QT_OK) return st;
     qt_context::Tables t;
     if ((st = ensure_tables(ctx, QT_FP64, N, &t)) != QT_OK) return st;

@@ -22,6 +22,9 @@ struct qt_context {
     bool timed = false;
     int64_t last_launches = 0;
     std::vector<hipStream_t> aux;                          // fork/join streams
+    // static phase tables exp(-i dt/2 V_static) per (l, colour), keyed by
+    // (precision, N, L, mass, alpha_s, dt)
+    std::map<std::vector<double>, void*> phase;
 };
 
 namespace qt {
@@ -68,9 +71,23 @@ struct DeviceGroups {
     GroupDesc* groups = nullptr;     // device
     std::vector<GroupDesc> host;     // host copy
 };
-qt_status upload_groups(const std::vector<const HostBatch*>& hb, int prec,
+qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb, int prec,
                         const std::vector<qt_results>& outs, bool with_Tn,
                         hipStream_t s, bool async_alloc, DeviceGroups* out);
+qt_status ensure_phase(qt_context* ctx, const HostBatch& hb, int prec, const void** out);
+
+// Device buffers for the per-trajectory results (no wave functions).
+struct ResultBuffers {
+    void* mem = nullptr;
+    size_t bytes = 0;
+    qt_results r{};
+};
+qt_status alloc_results(int64_t n, ResultBuffers* rb);
+size_t result_bytes(int64_t n);
+qt_status copy_results(const qt_results& src, const qt_results& dst, int64_t n, hipMemcpyKind kind,
+                       hipStream_t s);
+qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb,
+                           const std::vector<qt_results>& outs, int prec, hipStream_t s);
 
 // LPT order of (group, index) items: longest remaining work first.
 void build_items(const std::vector<const HostBatch*>& hb, std::vector<int32_t>* ig,

@@ -59,6 +59,8 @@ fused_launcher fused_get(int prec, int N, int W);
 int fused_occupancy(int prec, int N, int W);
 
 hipError_t launch_queue_reset(int32_t* q, hipStream_t s);
+// complex values of the precision -> interleaved FP64 pairs
+hipError_t launch_widen(const void* src, int prec, double* dst, int64_t count, hipStream_t s);
 
 // Plain (unfused, FP64) form: one kernel per sub-step.
 struct PlainArgs {

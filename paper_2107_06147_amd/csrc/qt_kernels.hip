@@ -343,7 +343,8 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
                                    first_r, min_gap);
         }
         if (g.st) {
-            if (!done) {
+            // checkpoint (the final state too, so a job can return it)
+            {
                 cx<R>* dst = static_cast<cx<R>*>(g.st_psi) + (size_t)idx * N;
                 sfor<0, R1>([&](auto Rr) QT_INL {
                     dst[ln.ja + Rr * T] = a[Rr];
@@ -362,6 +363,28 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
 }
 
 __global__ void queue_reset_kernel(int32_t* q) { *q = 0; }
+
+template <class R>
+__global__ void widen_kernel(const cx<R>* src, double* dst, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    dst[2 * i] = (double)src[i].re;
+    dst[2 * i + 1] = (double)src[i].im;
+}
+
+hipError_t launch_widen(const void* src, int prec, double* dst, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((count + 255) / 256));
+    if (prec == QT_FP32_BULK)
+        hipLaunchKernelGGL(widen_kernel<float>, grid, dim3(256), 0, s,
+                           static_cast<const cx<float>*>(src), dst, count);
+    else
+        hipLaunchKernelGGL(widen_kernel<double>, grid, dim3(256), 0, s,
+                           static_cast<const cx<double>*>(src), dst, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_queue_reset(int32_t* q, hipStream_t s)
 {

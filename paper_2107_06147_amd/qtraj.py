@@ -239,6 +239,14 @@ class Context:
     """Owns a qt_context on one HIP device."""
 
     def __init__(self, device=0):
+        # torch carries its own HIP runtime; it has to bring the device up
+        # before this library's runtime does, or torch will not see it
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         h = _VP()
         check(lib().qt_context_create(int(device), C.byref(h)), "qt_context_create")
         self.h = h
@@ -313,3 +321,118 @@ def run_many(ctx, cfgs, precision=QT_FP32_BULK, want_psi=False, stream=None):
         RS[i] = r
     check(lib().qt_run_many(ctx.h, k, P, TT, IN, B, RS, _stream_handle(stream)), "qt_run_many")
     return outs
+
+
+# -------------------------------------------------------------------- jobs --
+
+class Job:
+    """Segmented run (qt_job_*): state checkpointed in device memory every
+    `segment_steps` steps; advance() replays a captured HIP graph."""
+
+    def __init__(self, ctx, cfg, precision=QT_FP32_BULK, segment_steps=1000, n_traj=None):
+        self._keep = []
+        self.ctx = ctx
+        self.cfg = cfg
+        self.n = int(cfg["n_traj"] if n_traj is None else n_traj)
+        p = physics(cfg)
+        tt = ttable(cfg, self._keep)
+        ini = init(cfg, self._keep)
+        b = batch(cfg, precision, QT_FORM_FUSED, self.n)
+        h = _VP()
+        check(lib().qt_job_create(ctx.h, C.byref(p), C.byref(tt), C.byref(ini), C.byref(b),
+                                  int(segment_steps), C.byref(h)), "qt_job_create")
+        self.h = h
+
+    def advance(self, steps, stream=None):
+        check(lib().qt_job_advance(self.h, int(steps), _stream_handle(stream)), "qt_job_advance")
+
+    def done(self):
+        d = C.c_int32()
+        check(lib().qt_job_done(self.h, C.byref(d)), "qt_job_done")
+        return bool(d.value)
+
+    def state_bytes(self):
+        n = C.c_size_t()
+        check(lib().qt_job_state_bytes(self.h, C.byref(n)), "qt_job_state_bytes")
+        return n.value
+
+    def save(self, dst_ptr, stream=None):
+        check(lib().qt_job_save(self.h, C.c_void_p(dst_ptr), _stream_handle(stream)), "qt_job_save")
+
+    def load(self, src_ptr, stream=None):
+        check(lib().qt_job_load(self.h, C.c_void_p(src_ptr), _stream_handle(stream)), "qt_job_load")
+
+    def results(self, want_psi=False, stream=None):
+        out, res = alloc_results(self.n, int(self.cfg["N"]), want_psi)
+        check(lib().qt_job_results(self.h, C.byref(res), _stream_handle(stream)), "qt_job_results")
+        return out
+
+    def close(self):
+        if self.h:
+            lib().qt_job_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ server --
+
+class Server:
+    """Continuous-batching server (qt_server_*)."""
+
+    def __init__(self, ctx, precision=QT_FP32_BULK, segment_steps=500, hbm_budget_bytes=0):
+        cfg = qt_server_cfg(int(hbm_budget_bytes), int(segment_steps), int(precision))
+        h = _VP()
+        check(lib().qt_server_create(ctx.h, C.byref(cfg), C.byref(h)), "qt_server_create")
+        self.h = h
+        self.precision = precision
+        self._pending = {}
+
+    def submit(self, cfg, n_traj=None):
+        keep = []
+        p = physics(cfg)
+        tt = ttable(cfg, keep)
+        ini = init(cfg, keep)
+        b = batch(cfg, self.precision, QT_FORM_FUSED, n_traj)
+        rid = C.c_uint64()
+        check(lib().qt_submit(self.h, C.byref(p), C.byref(tt), C.byref(ini), C.byref(b),
+                              C.byref(rid)), "qt_submit")
+        self._pending[rid.value] = (int(b.n_traj), int(cfg["N"]))
+        return rid.value
+
+    def poll(self, rid):
+        d = C.c_int32()
+        check(lib().qt_poll(self.h, C.c_uint64(rid), C.byref(d)), "qt_poll")
+        return bool(d.value)
+
+    def wait(self, rid, timeout_s=-1.0, want_psi=False):
+        n, N = self._pending[rid]
+        out, res = host_results(n, N, want_psi)
+        check(lib().qt_wait(self.h, C.c_uint64(rid), C.byref(res), float(timeout_s)), "qt_wait")
+        del self._pending[rid]
+        if want_psi:
+            out["psi"] = out["psi"][..., 0] + 1j * out["psi"][..., 1]
+        return out
+
+    def cancel(self, rid):
+        check(lib().qt_cancel(self.h, C.c_uint64(rid)), "qt_cancel")
+
+    def stats(self):
+        st = qt_stats()
+        check(lib().qt_server_stats(self.h, C.byref(st)), "qt_server_stats")
+        return {k: getattr(st, k) for k, _ in qt_stats._fields_}
+
+    def close(self):
+        if self.h:
+            lib().qt_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

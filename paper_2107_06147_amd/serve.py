@@ -1,0 +1,73 @@
+"""Served request stream: replays seeded Poisson arrivals against the
+continuous-batching server and reports latency percentiles and throughput.
+
+The workload is the served stream of the benchmark suite (see
+`workloads.c4_requests`): Poisson arrivals, lognormal trajectory counts, N in
+{1024, 2048}, per-request random-walk temperature tables.  `rate_scale`
+stretches the inter-arrival times so that the offered load can be set as a
+fraction of the device's capacity; `steps_cap` optionally shortens every
+request's time evolution (stated in the report).
+"""
+from __future__ import annotations
+
+import threading
+import time
+
+import numpy as np
+
+from paper_2107_06147_amd import qtraj as qt
+from paper_2107_06147_amd import workloads as W
+
+
+def replay(ctx, requests, precision=qt.QT_FP32_BULK, segment_steps=500, rate_scale=1.0,
+           steps_cap=None, hbm_budget_bytes=0):
+    """Submits `requests` [(arrival_s, cfg)] at their (scaled) arrival times,
+    waits for all, returns per-request latencies and the server's stats."""
+    srv = qt.Server(ctx, precision=precision, segment_steps=segment_steps,
+                    hbm_budget_bytes=hbm_budget_bytes)
+    ids = []
+    t_submit = {}
+    lat = {}
+    lock = threading.Lock()
+    start = time.perf_counter()
+    offered = 0
+    for (t_arr, cfg) in requests:
+        if steps_cap is not None:
+            cfg = dict(cfg, max_steps=int(steps_cap))
+        delay = start + t_arr * rate_scale - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        rid = srv.submit(cfg)
+        with lock:
+            t_submit[rid] = time.perf_counter()
+        ids.append(rid)
+        offered += int(cfg["n_traj"])
+    results = {}
+    for rid in ids:
+        results[rid] = srv.wait(rid)
+        lat[rid] = time.perf_counter() - t_submit[rid]
+    wall = time.perf_counter() - start
+    stats = srv.stats()
+    srv.close()
+    v = np.array(sorted(lat.values()))
+    return {
+        "requests": len(ids),
+        "trajectories": offered,
+        "p50_latency_s": float(np.percentile(v, 50)) if len(v) else None,
+        "p99_latency_s": float(np.percentile(v, 99)) if len(v) else None,
+        "server_p50_latency_s": stats["p50_latency_s"],
+        "server_p99_latency_s": stats["p99_latency_s"],
+        "traj_steps": stats["traj_steps"],
+        "traj_steps_per_s_busy": stats["traj_steps_per_s"],
+        "traj_steps_per_s_wall": stats["traj_steps"] / wall if wall > 0 else None,
+        "wall_s": wall,
+    }, results
+
+
+def bench_stream(ctx, duration_s=6.0, rate_scale=1.0, steps_cap=None, segment_steps=500):
+    reqs = W.c4_requests(duration_s=duration_s)
+    rep, _ = replay(ctx, reqs, rate_scale=rate_scale, steps_cap=steps_cap,
+                    segment_steps=segment_steps)
+    rep.update({"arrival_rate_per_s": 20.0 / rate_scale, "duration_s": duration_s,
+                "steps_cap": steps_cap, "segment_steps": segment_steps})
+    return rep

@@ -1,0 +1,150 @@
+"""Segmented runs (checkpoints, HIP-graph replay, save/restore), uneven
+batches in one job, and the continuous-batching server.  Marked `gpu`."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_06147_amd import qtraj as qt
+from paper_2107_06147_amd import workloads as W
+from tests.gpu_parity import compare, gpu_run
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = qt.QT_FP64, qt.QT_FP32_BULK
+KEYS = ("norm", "first_r", "overlap", "survival", "mean_r", "l", "color", "n_jumps", "status",
+        "steps_done", "min_gap")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = qt.Context(0)
+    yield c
+    c.close()
+
+
+def _cfg():
+    return W.base(N=512, L=20.0, dt=0.001, kappa_hat=20.0, n_traj=40, seed=17,
+                  init_kind=W.INIT_GAUSSIAN, init_width=1.0, **W.constant_T(0.5, 300))
+
+
+def _same(a, b, keys=KEYS + ("psi",)):
+    for k in keys:
+        if k in a and k in b:
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_segments_equal_single_run(ctx, prec):
+    import torch
+    cfg = _cfg()
+    ref = gpu_run(ctx, cfg, prec)
+    job = qt.Job(ctx, cfg, precision=prec, segment_steps=37)
+    job.advance(300)
+    assert job.done()
+    out = qt.to_numpy(job.results(want_psi=True))
+    torch.cuda.synchronize()
+    job.close()
+    _same(ref, out)
+
+
+def test_graph_replay_and_checkpoint_resume(ctx):
+    import torch
+    cfg = _cfg()
+    ref = gpu_run(ctx, cfg, F32)
+    a = qt.Job(ctx, cfg, precision=F32, segment_steps=25)
+    for _ in range(3):                     # the same captured graph, three times
+        a.advance(50)
+    assert not a.done()
+    blob = torch.empty(a.state_bytes(), dtype=torch.uint8)        # host checkpoint
+    a.save(blob.data_ptr())
+    torch.cuda.synchronize()
+    a.close()
+    b = qt.Job(ctx, cfg, precision=F32, segment_steps=25)
+    b.load(blob.data_ptr())
+    b.advance(150)
+    assert b.done()
+    out = qt.to_numpy(b.results(want_psi=True))
+    torch.cuda.synchronize()
+    b.close()
+    _same(ref, out)
+
+
+def test_job_fp64_matches_oracle(ctx):
+    import torch
+    cfg = _cfg()
+    ref = oracle.run(cfg, want_psi=True)
+    job = qt.Job(ctx, cfg, precision=F64, segment_steps=100)
+    job.advance(300)
+    out = qt.to_numpy(job.results(want_psi=True))
+    torch.cuda.synchronize()
+    job.close()
+    compare(ref, out, F64, label="job fp64")
+
+
+def test_run_many_uneven_equals_separate_runs(ctx):
+    """Batches of N = 1024/2048/4096 with different lifetimes in one job give
+    bitwise the results of separate runs, and match the oracle (FP64)."""
+    import torch
+    cfgs = W.c3_uneven(n_traj=9)
+    for i, c in enumerate(cfgs):
+        c["max_steps"] = 40 + 30 * i          # uneven lifetimes
+        c["n_traj"] = 2
+    outs = qt.run_many(ctx, cfgs, precision=F64, want_psi=True)
+    torch.cuda.synchronize()
+    for c, o in zip(cfgs, outs):
+        alone = gpu_run(ctx, c, F64)
+        _same(alone, qt.to_numpy(o))
+    for c, o in list(zip(cfgs, outs))[:3]:
+        compare(oracle.run(c, want_psi=True), qt.to_numpy(o), F64, label="many N=%d" % c["N"])
+
+
+# ------------------------------------------------------------------ server --
+
+def _requests():
+    tau, T = W.random_walk_table(np.random.default_rng(5))
+    r1 = W.base(N=1024, L=20.0, dt=0.001, kappa_hat=4.0, n_traj=30, seed=101,
+                init_kind=W.INIT_GAUSSIAN, init_width=1.0, tau=tau, T=T, tau_start=float(tau[0]),
+                T_final=0.0, max_steps=200)
+    r2 = W.base(N=2048, L=40.0, dt=0.001, kappa_hat=8.0, n_traj=20, seed=102,
+                init_kind=W.INIT_GAUSSIAN, init_width=1.0, **W.constant_T(0.45, 150))
+    r3 = W.base(N=1024, L=20.0, dt=0.001, kappa_hat=4.0, gamma_hat=-2.0, n_traj=25, seed=103,
+                init_kind=W.INIT_COULOMB, **W.constant_T(0.35, 260))
+    return [r1, r2, r3]
+
+
+def test_server_alone_vs_mix_bitwise(ctx):
+    """Each request's result in the concurrent mix equals its result alone."""
+    reqs = _requests()
+    alone = [gpu_run(ctx, c, F32) for c in reqs]
+    srv = qt.Server(ctx, precision=F32, segment_steps=64)
+    ids = [srv.submit(c) for c in reqs]
+    outs = [srv.wait(i, timeout_s=120, want_psi=True) for i in ids]
+    st = srv.stats()
+    srv.close()
+    for a, o in zip(alone, outs):
+        _same(a, o)
+    assert st["completed"] == 3 and st["p99_latency_s"] >= st["p50_latency_s"] > 0
+    assert st["traj_steps"] == sum(int(a["steps_done"].sum()) for a in alone)
+
+
+def test_server_rejects_bad_requests_and_keeps_running(ctx):
+    srv = qt.Server(ctx, precision=F32, segment_steps=50, hbm_budget_bytes=64 << 20)
+    good = _requests()[0]
+    rid = srv.submit(good)
+    bad = dict(good, N=300)
+    with pytest.raises(qt.QtError) as e:
+        srv.submit(bad)
+    assert e.value.status == qt.QT_EINVAL
+    huge = dict(good, N=4096, L=80.0, n_traj=200000)
+    with pytest.raises(qt.QtError) as e:
+        srv.submit(huge)
+    assert e.value.status == qt.QT_ENOMEM
+    long = dict(good, max_steps=100000)
+    rid2 = srv.submit(long)
+    srv.cancel(rid2)
+    out = srv.wait(rid, timeout_s=120)
+    assert np.all(out["steps_done"] == 200)
+    with pytest.raises(qt.QtError) as e:
+        srv.wait(rid2, timeout_s=120)
+    assert e.value.status == qt.QT_ECANCELED
+    srv.close()
