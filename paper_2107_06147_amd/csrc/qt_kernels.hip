@@ -22,9 +22,51 @@
 
 namespace qt {
 
-__device__ __forceinline__ float qexpm1(float x) { return expm1f(x); }
+// FP32 exp(x) - 1 for x <= 0 without branches: the Taylor series to x^8 on
+// x > -1/2 (remainder < 1e-8 relative), exp2 - 1 below (then |result| > 0.39
+// and the absolute error of exp2 is relative error ~1e-7).
+__device__ __forceinline__ float qexpm1(float x)
+{
+    float p = 1.0f / 40320.0f;
+    p = fmaf(p, x, 1.0f / 5040.0f);
+    p = fmaf(p, x, 1.0f / 720.0f);
+    p = fmaf(p, x, 1.0f / 120.0f);
+    p = fmaf(p, x, 1.0f / 24.0f);
+    p = fmaf(p, x, 1.0f / 6.0f);
+    p = fmaf(p, x, 0.5f);
+    p = fmaf(p, x, 1.0f);
+    p = p * x;
+    const float e = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.0f;
+    return x > -0.5f ? p : e;
+}
 __device__ __forceinline__ double qexpm1(double x) { return expm1(x); }
-__device__ __forceinline__ void qsincos(float x, float* s, float* c) { sincosf(x, s, c); }
+
+// FP32 sin and cos without branches: reduction by multiples of pi/2 with a
+// two-constant (Cody-Waite) split of pi/2, then the Taylor series of sin to
+// f^9 and cos to f^10 on |f| <= pi/4 (remainders < 2e-9).  Meant for the
+// moderate arguments of the thermal phase (|x| < 1e4).
+__device__ __forceinline__ void qsincos(float x, float* s, float* c)
+{
+    const float k = rintf(x * 0.636619772367581343f);
+    float f = fmaf(-k, 1.57079637050628662109375f, x);
+    f = fmaf(-k, -4.37113900018624283e-8f, f);
+    const float f2 = f * f;
+    float sp = -1.0f / 362880.0f;
+    sp = fmaf(sp, f2, 1.0f / 5040.0f);
+    sp = fmaf(sp, f2, -1.0f / 120.0f);
+    sp = fmaf(sp, f2, 1.0f / 6.0f);
+    sp = fmaf(-sp * f2, f, f);
+    float cp = -1.0f / 3628800.0f;
+    cp = fmaf(cp, f2, 1.0f / 40320.0f);
+    cp = fmaf(cp, f2, -1.0f / 720.0f);
+    cp = fmaf(cp, f2, 1.0f / 24.0f);
+    cp = fmaf(cp, f2, -0.5f);
+    cp = fmaf(cp, f2, 1.0f);
+    const int q = (int)k & 3;
+    const float ss = (q & 1) ? cp : sp, cc = (q & 1) ? sp : cp;
+    *s = (q & 2) ? -ss : ss;
+    *c = ((q + 1) & 2) ? -cc : cc;
+}
 __device__ __forceinline__ void qsincos(double x, double* s, double* c) { sincos(x, s, c); }
 
 // Sum of K values over the workgroup, every lane receives all K sums.
@@ -55,40 +97,35 @@ __device__ __forceinline__ void block_sum_vec(double* x, double* red)
 
 // exp(-i (dt/2) [V_coulomb(r) + l(l+1)/(M r^2)]): the time-independent part
 // of the half-step factor (appendix "Munich potential").  The host computes
-// it in FP64 for every (l, colour) with l <= l_tab (shared by all
-// trajectories of a grid); a trajectory loads its row at the start and
-// after each jump.
-template <class R, int N, int W>
-__device__ __forceinline__ void load_phase(cx<R>* pa, cx<R>* pb, const Lanes<N, W>& ln,
-                                           const GroupDesc& g, int l, int c)
+// it in FP64 for every (l, colour) with l <= l_tab, shared by all
+// trajectories of a grid; a half-step reads the row of its (l, colour) (L1/L2
+// resident: few rows are in use at a time).
+template <class R, int N>
+__device__ __forceinline__ const cx<R>* phase_row(const GroupDesc& g, int l, int c)
 {
-    constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
-    const cx<R>* row = static_cast<const cx<R>*>(g.phase) + (size_t)(2 * l + c) * N;
-    sfor<0, R1>([&](auto Rr) QT_INL {
-        pa[Rr] = row[ln.ja + Rr * T];
-        pb[Rr] = row[ln.jb + Rr * T];
-    });
+    return static_cast<const cx<R>*>(g.phase) + (size_t)(2 * l + c) * N;
 }
 
 // u_m <- P_m exp(z r_m^2) u_m, z = zr + i zi: the half-step factor
-// exp(-i V_eff dt/2) split into its static phase P and the part that
-// follows the temperature, z = -(dt/2) c (kappa + i gamma) with c = 1/2
+// exp(-i V_eff dt/2) split into its static phase P (table row) and the part
+// that follows the temperature, z = -(dt/2) c (kappa + i gamma) with c = 1/2
 // (singlet) or 7/32 (octet).  exp(z r^2) is applied as u + (exp(z r^2) - 1) u
 // with the small difference computed by expm1 (and, for the phase,
 // cos y - 1 = -2 sin^2(y/2)), so that its rounding is relative to the
 // difference and does not bias the norm step after step.
-template <class R, int N, int W>
-__device__ __forceinline__ void apply_half_step(cx<R>* a, cx<R>* b, const cx<R>* pa,
-                                                const cx<R>* pb, const Lanes<N, W>& ln, R dr,
-                                                R zr, R zi, bool has_gamma)
+template <class R, int N, int W, bool GAMMA>
+__device__ __forceinline__ void apply_half_step_g(cx<R>* a, cx<R>* b, const cx<R>* row,
+                                                  const Lanes<N, W>& ln, R dr, R zr, R zi)
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
-    auto apply = [&](int m, cx<R> p, cx<R> u) QT_INL {
+    row = opaque(row);
+    auto apply = [&](int m, cx<R> u) QT_INL {
+        const cx<R> p = row[m];
         const R rm = R(m) * dr;
         const R r2 = rm * rm;
         const R em1 = qexpm1(zr * r2);
         cx<R> q;
-        if (has_gamma) {
+        if constexpr (GAMMA) {
             R s2, c2;
             qsincos(R(0.5) * zi * r2, &s2, &c2);
             const R cm1 = R(-2) * s2 * s2;
@@ -99,10 +136,19 @@ __device__ __forceinline__ void apply_half_step(cx<R>* a, cx<R>* b, const cx<R>*
         return p * (u + q * u);
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
-        a[Rr] = apply(ln.ja + Rr * T, pa[Rr], a[Rr]);
-        b[Rr] = apply(ln.jb + Rr * T, pb[Rr], b[Rr]);
+        a[Rr] = apply(ln.ja + Rr * T, a[Rr]);
+        b[Rr] = apply(ln.jb + Rr * T, b[Rr]);
         if constexpr ((Rr & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     });
+}
+
+template <class R, int N, int W>
+__device__ __forceinline__ void apply_half_step(cx<R>* a, cx<R>* b, const cx<R>* row,
+                                                const Lanes<N, W>& ln, R dr, R zr, R zi,
+                                                bool has_gamma)
+{
+    if (has_gamma) apply_half_step_g<R, N, W, true>(a, b, row, ln, dr, zr, zi);
+    else apply_half_step_g<R, N, W, false>(a, b, row, ln, dr, zr, zi);
 }
 
 // u <- u + f u (f small: a relative correction)
@@ -264,9 +310,7 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
         step = uniform(step); r = uniform(r); norm = uniform(norm);
         int64_t end = uniform(g.n_steps);
         if (A.seg_steps > 0 && step + A.seg_steps < end) end = step + A.seg_steps;
-        cx<R> pa[R1], pb[R1];
         if (l > g.l_tab) status = QT_TRAJ_LMAX;
-        else load_phase<R, N, W>(pa, pb, ln, g, l, c);
         const bool has_gamma = g.gamma_hat != 0.0;
         const R dr = R(g.dr);
         int cur = 0;
@@ -280,8 +324,9 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
             const double cc = (c == QT_SINGLET) ? 0.5 : 7.0 / 32.0;
             const R zr = R(-0.5 * g.dt * cc * g.kappa_hat * T3);
             const R zi = R(-0.5 * g.dt * cc * g.gamma_hat * T3);
+            const cx<R>* row = phase_row<R, N>(g, l, c);
 
-            apply_half_step<R, N, W>(a, b, pa, pb, ls, dr, zr, zi, has_gamma);
+            apply_half_step<R, N, W>(a, b, row, ls, dr, zr, zi, has_gamma);
             double n_in = 0.0;
             if constexpr (kRenorm) n_in = block_sum<W>(sum_abs2<R, N, W>(a, b), red);
             const cx<R>* tw_n = opaque(tw);
@@ -293,13 +338,13 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
                 // reduction
                 double x[2];
                 x[0] = sum_abs2<R, N, W>(a, b);
-                apply_half_step<R, N, W>(a, b, pa, pb, ls, dr, zr, zi, has_gamma);
+                apply_half_step<R, N, W>(a, b, row, ls, dr, zr, zi, has_gamma);
                 x[1] = sum_abs2<R, N, W>(a, b);
                 block_sum_vec<W, 2>(x, red);
                 add_scaled<R, N, W>(a, b, R(sqrt(n_in / x[0]) - 1.0));
                 norm = g.dr * x[1] * (n_in / x[0]);
             } else {
-                apply_half_step<R, N, W>(a, b, pa, pb, ls, dr, zr, zi, has_gamma);
+                apply_half_step<R, N, W>(a, b, row, ls, dr, zr, zi, has_gamma);
                 norm = g.dr * block_sum<W>(sum_abs2<R, N, W>(a, b), red);
             }
             step = n + 1;
@@ -334,7 +379,6 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
                     status = QT_TRAJ_LMAX;
                     break;
                 }
-                load_phase<R, N, W>(pa, pb, ls, g, l, c);
             }
         }
         const bool done = status != QT_TRAJ_OK || step >= g.n_steps;
