@@ -69,6 +69,27 @@ __device__ __forceinline__ const T* opaque(const T* p)
     return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
 }
 
+// Loads of table element i through a global-address-space pointer with a
+// 32-bit byte offset: the compiler then addresses them as scalar base +
+// one vector register (no 64-bit address arithmetic per load, and no flat
+// accesses that would also hold up the LDS wait counter).
+#define QT_GLOBAL __attribute__((address_space(1)))
+template <class R>
+__device__ __forceinline__ cx<R> ldg(const cx<R>* p, uint32_t i)
+{
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(const QT_GLOBAL v2*)((const QT_GLOBAL char*)p + i * (uint32_t)sizeof(cx<R>));
+    cx<R> z;
+    z.re = v.x;
+    z.im = v.y;
+    return z;
+}
+template <class R>
+__device__ __forceinline__ R ldg(const R* p, uint32_t i)
+{
+    return *(const QT_GLOBAL R*)((const QT_GLOBAL char*)p + i * (uint32_t)sizeof(R));
+}
+
 // Same for the lane id: address arithmetic derived from it is then redone
 // next to its use in every step instead of being kept live in registers
 // across the whole time loop.
@@ -89,6 +110,12 @@ __device__ __forceinline__ cx<R> pick(bool c, cx<R> x, cx<R> y)
 // LDS index with one pad element every 16 (spreads power-of-two strides
 // over the banks).
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+// pad(base + C) for a compile-time C, as a constant offset from pad(base).
+// Valid when the low four bits of base and C do not carry into bit 4, which
+// holds for every access below: each one is base + C with base & 15 and C
+// together below 16, or C a multiple of 16 (all sizes are powers of two).
+// The offset then goes into the LDS instruction's immediate field.
+template <int C> constexpr int padc() { return C + (C >> 4); }
 template <int N> constexpr int padded_len() { return N + N / 16; }
 
 // cos(2 pi k / 64), k = 0..63
@@ -242,7 +269,7 @@ __device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R
             const int k = j & (NS - 1);
             sfor<1, RAD>([&](auto Rr) QT_INL {
                 constexpr int r = Rr;
-                v[q * RAD + r] = v[q * RAD + r] * tw[r * k * (N / (NS * RAD))];
+                v[q * RAD + r] = v[q * RAD + r] * ldg(tw, r * k * (N / (NS * RAD)));
             });
         }
         dft<RAD>(v + q * RAD);
@@ -251,8 +278,8 @@ __device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R
         sfor<0, B>([&](auto Q) QT_INL {
             constexpr int q = Q;
             const int j = bfly(q);
-            const int base = (j / NS) * NS * RAD + (j & (NS - 1));
-            sfor<0, RAD>([&](auto Rr) QT_INL { buf[pad(base + Rr * NS)] = v[q * RAD + Rr]; });
+            cx<R>* dst = buf + pad((j / NS) * NS * RAD + (j & (NS - 1)));
+            sfor<0, RAD>([&](auto Rr) QT_INL { dst[padc<Rr * NS>()] = v[q * RAD + Rr]; });
         });
         __syncthreads();
         constexpr int RAD2 = PL::radix(p + 1);
@@ -261,7 +288,8 @@ __device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R
         sfor<0, B2>([&](auto Q) QT_INL {
             constexpr int q = Q;
             const int j = edge2 ? (q == 0 ? ln.ja : ln.jb) : q * W + ln.t;
-            sfor<0, RAD2>([&](auto Rr) QT_INL { v[q * RAD2 + Rr] = buf[pad(j + Rr * (N / RAD2))]; });
+            const cx<R>* src = buf + pad(j);
+            sfor<0, RAD2>([&](auto Rr) QT_INL { v[q * RAD2 + Rr] = src[padc<Rr * (N / RAD2)>()]; });
         });
         __syncthreads();
         fft_passes<R, N, W, p + 1>(v, ln, buf, tw);
@@ -372,10 +400,10 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* __restrict__ s
         constexpr int r = Rr;
         cx<R> xa = a[r];
         cx<R> ma = pick(lane0, a[(R1 - r) % R1], b[R1 - 1 - r]);
-        v[r] = scale(xa + ma, sines[ln.ja + r * T]) + scale(xa - ma, half);
+        v[r] = scale(xa + ma, ldg(sines, ln.ja + r * T)) + scale(xa - ma, half);
         cx<R> xb = b[r];
         cx<R> mb = pick(lane0, b[R1 - 1 - r], a[R1 - 1 - r]);
-        v[R1 + r] = scale(xb + mb, sines[ln.jb + r * T]) + scale(xb - mb, half);
+        v[R1 + r] = scale(xb + mb, ldg(sines, ln.jb + r * T)) + scale(xb - mb, half);
     });
     fft_passes<R, N, W, 0>(v, ln, buf, tw);
     // F * kin, with the low part of a double-float kinetic factor in FP32
@@ -385,8 +413,8 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* __restrict__ s
         if constexpr (LO) kin_lo = opaque(kin_lo);
     }
     auto kmul = [&](cx<R> F, int m) QT_INL {
-        cx<R> G = F * kin[m];
-        if constexpr (LO) G = G + F * kin_lo[m];
+        cx<R> G = F * ldg(kin, m);
+        if constexpr (LO) G = G + F * ldg(kin_lo, m);
         return G;
     };
     // post-processing: pairs (k, N-k), even outputs and differences D_k
@@ -398,8 +426,9 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* __restrict__ s
             const int k = ln.ja + r * T;
             cx<R> F = mul_ihalf(y - yp);
             if constexpr (KIN) F = kmul(F, 2 * k);
-            buf[pad(2 * k)] = F;
-            buf[pad(2 * k + 1)] = scale(y + yp, half);
+            cx<R>* dst = buf + pad(2 * ln.ja);
+            dst[padc<2 * r * T>()] = F;
+            dst[padc<2 * r * T>() + 1] = scale(y + yp, half);
         }
         {
             cx<R> y = v[R1 + r];
@@ -407,8 +436,9 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* __restrict__ s
             const int k = ln.jb + r * T;
             cx<R> F = mul_ihalf(y - yp);
             if constexpr (KIN) F = kmul(F, 2 * k);
-            buf[pad(2 * k)] = F;
-            buf[pad(2 * k + 1)] = scale(y + yp, half);
+            cx<R>* dst = buf + pad(2 * ln.jb);
+            dst[padc<2 * r * T>()] = F;
+            dst[padc<2 * r * T>() + 1] = scale(y + yp, half);
         }
     });
     __syncthreads();
@@ -417,9 +447,9 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* __restrict__ s
     const cx<R> d0 = buf[pad(1)];
     cx<R> pre[CH];
     cx<R> run = mk(R(0), R(0));
+    cx<R>* chunk = buf + pad(2 * CH * ln.t);
     sfor<0, CH>([&](auto I) QT_INL {
-        const int k = ln.t * CH + I;
-        run = run + buf[pad(2 * k + 1)];
+        run = run + chunk[padc<2 * I + 1>()];
         pre[I] = run;
     });
     const cx<R> off = block_exclusive_scan<W>(run, wsum) - scale(d0, half);
@@ -427,13 +457,17 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* __restrict__ s
         const int k = ln.t * CH + I;
         cx<R> F = pre[I] + off;
         if constexpr (KIN) F = kmul(F, 2 * k + 1);
-        buf[pad(2 * k + 1)] = F;
+        chunk[padc<2 * I + 1>()] = F;
     });
     __syncthreads();
-    sfor<0, R1>([&](auto Rr) QT_INL {
-        a[Rr] = buf[pad(ln.ja + Rr * T)];
-        b[Rr] = buf[pad(ln.jb + Rr * T)];
-    });
+    {
+        const cx<R>* sa = buf + pad(ln.ja);
+        const cx<R>* sb = buf + pad(ln.jb);
+        sfor<0, R1>([&](auto Rr) QT_INL {
+            a[Rr] = sa[padc<Rr * T>()];
+            b[Rr] = sb[padc<Rr * T>()];
+        });
+    }
     __syncthreads();
 }
 

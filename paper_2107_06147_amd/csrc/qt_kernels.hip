@@ -22,9 +22,9 @@
 
 namespace qt {
 
-// FP32 exp(x) - 1 for x <= 0 without branches: the Taylor series to x^8 on
-// x > -1/2 (remainder < 1e-8 relative), exp2 - 1 below (then |result| > 0.39
-// and the absolute error of exp2 is relative error ~1e-7).
+// FP32 exp(x) - 1 without branches: the Taylor series to x^8 on |x| < 1/2
+// (remainder < 2e-8 relative), exp2 - 1 elsewhere (there |result| > 0.39 and
+// the absolute error of exp2 is a relative error ~1e-7).
 __device__ __forceinline__ float qexpm1(float x)
 {
     float p = 1.0f / 40320.0f;
@@ -37,7 +37,7 @@ __device__ __forceinline__ float qexpm1(float x)
     p = fmaf(p, x, 1.0f);
     p = p * x;
     const float e = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.0f;
-    return x > -0.5f ? p : e;
+    return fabsf(x) < 0.5f ? p : e;
 }
 __device__ __forceinline__ double qexpm1(double x) { return expm1(x); }
 
@@ -106,49 +106,147 @@ __device__ __forceinline__ const cx<R>* phase_row(const GroupDesc& g, int l, int
     return static_cast<const cx<R>*>(g.phase) + (size_t)(2 * l + c) * N;
 }
 
-// u_m <- P_m exp(z r_m^2) u_m, z = zr + i zi: the half-step factor
-// exp(-i V_eff dt/2) split into its static phase P (table row) and the part
-// that follows the temperature, z = -(dt/2) c (kappa + i gamma) with c = 1/2
-// (singlet) or 7/32 (octet).  exp(z r^2) is applied as u + (exp(z r^2) - 1) u
-// with the small difference computed by expm1 (and, for the phase,
-// cos y - 1 = -2 sin^2(y/2)), so that its rounding is relative to the
-// difference and does not bias the norm step after step.
-template <class R, int N, int W, bool GAMMA>
-__device__ __forceinline__ void apply_half_step_g(cx<R>* a, cx<R>* b, const cx<R>* row,
-                                                  const Lanes<N, W>& ln, R dr, R zr, R zi)
+// FP32 exp(x) - 1 on |x| <= 1/2: the Taylor series to x^8 (remainder
+// < 2e-8 relative).  FP64 uses the library function.
+__device__ __forceinline__ float expm1_small(float x)
+{
+    float p = 1.0f / 40320.0f;
+    p = fmaf(p, x, 1.0f / 5040.0f);
+    p = fmaf(p, x, 1.0f / 720.0f);
+    p = fmaf(p, x, 1.0f / 120.0f);
+    p = fmaf(p, x, 1.0f / 24.0f);
+    p = fmaf(p, x, 1.0f / 6.0f);
+    p = fmaf(p, x, 0.5f);
+    p = fmaf(p, x, 1.0f);
+    return p * x;
+}
+__device__ __forceinline__ double expm1_small(double x) { return expm1(x); }
+
+// FP32 sin and cos on |x| <= pi/4: Taylor series to x^9 and x^10
+// (remainders < 2e-9).  FP64 uses the library function.
+__device__ __forceinline__ void sincos_small(float x, float* s, float* c)
+{
+    const float x2 = x * x;
+    float sp = -1.0f / 362880.0f;
+    sp = fmaf(sp, x2, 1.0f / 5040.0f);
+    sp = fmaf(sp, x2, -1.0f / 120.0f);
+    sp = fmaf(sp, x2, 1.0f / 6.0f);
+    *s = fmaf(-sp * x2, x, x);
+    float cp = -1.0f / 3628800.0f;
+    cp = fmaf(cp, x2, 1.0f / 40320.0f);
+    cp = fmaf(cp, x2, -1.0f / 720.0f);
+    cp = fmaf(cp, x2, 1.0f / 24.0f);
+    cp = fmaf(cp, x2, -0.5f);
+    *c = fmaf(cp, x2, 1.0f);
+}
+__device__ __forceinline__ void sincos_small(double x, double* s, double* c) { sincos(x, s, c); }
+
+// The half-step factor exp(-i V_eff(r_m) dt/2) of one time step is
+//   P_m exp(z r_m^2),   z = zr + i zi = -(dt/2) c (kappa + i gamma) T^3,
+// c = 1/2 (singlet) or 7/32 (octet), P_m the static phase (table row).  It is
+// applied as two diagonal factors: the real damping D_m = exp(zr r_m^2),
+// applied as u + (D_m - 1) u with D_m - 1 from expm1 so that its rounding is
+// relative to the (small) difference and does not bias the norm step after
+// step, and the phase C_m = P_m exp(i zi r_m^2), of modulus one.  The step is
+//   D C [DST kin DST] C D,
+// the bracket and C are unitary.  FP32-bulk renormalises C [DST kin DST] C
+// as a whole to the norm it receives, which also absorbs the modulus error of
+// C_m in FP32.  FAST: every argument is small (|zr| r^2 <= 1/2, |zi| r^2 <=
+// pi/4 on the whole grid: a per-step, wave-uniform decision), so short
+// series suffice.
+template <class R, bool GAMMA, bool FAST>
+struct HalfStep {
+    const cx<R>* row;
+    R dr, zr, zi;
+    __device__ __forceinline__ R r2(int m) const
+    {
+        const R rm = R(m) * dr;
+        return rm * rm;
+    }
+    __device__ __forceinline__ R em1(R x2) const
+    {
+        return FAST ? expm1_small(zr * x2) : qexpm1(zr * x2);
+    }
+    __device__ __forceinline__ cx<R> phase(int m, R x2) const
+    {
+        const cx<R> p = ldg(row, m);
+        if constexpr (GAMMA) {
+            R s, c;
+            if constexpr (FAST) sincos_small(zi * x2, &s, &c);
+            else qsincos(zi * x2, &s, &c);
+            return p * mk(c, s);
+        } else {
+            return p;
+        }
+    }
+};
+
+// First half-step: u <- C D u.  Returns this lane's part of sum |D u|^2 (the
+// norm the unitary block receives) when SUM; stores C_m in `fac` (this
+// lane's slots, no other lane reads them) when CACHE.
+template <class R, int N, int W, bool GAMMA, bool FAST, bool CACHE, bool SUM>
+__device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const HalfStep<R, GAMMA, FAST>& h,
+                                             const Lanes<N, W>& ln, cx<R>* fac)
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
-    row = opaque(row);
-    auto apply = [&](int m, cx<R> u) QT_INL {
-        const cx<R> p = row[m];
-        const R rm = R(m) * dr;
-        const R r2 = rm * rm;
-        const R em1 = qexpm1(zr * r2);
-        cx<R> q;
-        if constexpr (GAMMA) {
-            R s2, c2;
-            qsincos(R(0.5) * zi * r2, &s2, &c2);
-            const R cm1 = R(-2) * s2 * s2;
-            q = mk(em1 * (R(1) + cm1) + cm1, (R(1) + em1) * (R(2) * s2 * c2));
-        } else {
-            q = mk(em1, R(0));
-        }
-        return p * (u + q * u);
+    double acc = 0.0;
+    cx<R>* mine = fac + ln.t;
+    auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
+        const R x2 = h.r2(m);
+        const cx<R> w = u + scale(u, h.em1(x2));
+        if constexpr (SUM) acc += abs2d(w);
+        const cx<R> C = h.phase(m, x2);
+        if constexpr (CACHE) mine[E * W] = C;
+        u = C * w;
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
-        a[Rr] = apply(ln.ja + Rr * T, a[Rr]);
-        b[Rr] = apply(ln.jb + Rr * T, b[Rr]);
+        apply(ln.ja + Rr * T, a[Rr], std::integral_constant<int, Rr>{});
+        apply(ln.jb + Rr * T, b[Rr], std::integral_constant<int, R1 + Rr>{});
+        if constexpr ((Rr & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    });
+    return acc;
+}
+
+// Second half-step: u <- D C u.  Adds this lane's sum |C u|^2 to x0 (when
+// SUM0) and sum |D C u|^2 to x1.
+template <class R, int N, int W, bool GAMMA, bool FAST, bool CACHE, bool SUM0>
+__device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const HalfStep<R, GAMMA, FAST>& h,
+                                            const Lanes<N, W>& ln, const cx<R>* fac, double& x0,
+                                            double& x1)
+{
+    constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
+    const cx<R>* mine = fac + ln.t;
+    auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
+        const R x2 = h.r2(m);
+        cx<R> C;
+        if constexpr (CACHE) C = mine[E * W];
+        else C = h.phase(m, x2);
+        const cx<R> w = C * u;
+        if constexpr (SUM0) x0 += abs2d(w);
+        u = w + scale(w, h.em1(x2));
+        x1 += abs2d(u);
+    };
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        apply(ln.ja + Rr * T, a[Rr], std::integral_constant<int, Rr>{});
+        apply(ln.jb + Rr * T, b[Rr], std::integral_constant<int, R1 + Rr>{});
         if constexpr ((Rr & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     });
 }
 
-template <class R, int N, int W>
-__device__ __forceinline__ void apply_half_step(cx<R>* a, cx<R>* b, const cx<R>* row,
-                                                const Lanes<N, W>& ln, R dr, R zr, R zi,
-                                                bool has_gamma)
+// Calls f(GAMMA, FAST) with the two decisions as compile-time constants (the
+// decisions are wave-uniform: one scalar branch).
+template <class F>
+__device__ __forceinline__ void with_factor_kind(bool gamma, bool fast, F&& f)
 {
-    if (has_gamma) apply_half_step_g<R, N, W, true>(a, b, row, ln, dr, zr, zi);
-    else apply_half_step_g<R, N, W, false>(a, b, row, ln, dr, zr, zi);
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (gamma) {
+        if (fast) f(T_{}, T_{});
+        else f(T_{}, F_{});
+    } else {
+        if (fast) f(F_{}, T_{});
+        else f(F_{}, F_{});
+    }
 }
 
 // u <- u + f u (f small: a relative correction)
@@ -256,6 +354,11 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
     __shared__ cx<R> wsum[W / 64];
     __shared__ double red[14 * (W / 64)];
     __shared__ int s_item;
+    // per-lane cache of the phase factors C_m between the two half-steps of a
+    // step, kept when it still leaves room for two workgroups per CU
+    constexpr bool kCache =
+        sizeof(cx<R>) * (padded_len<N>() + N) <= 80u * 1024u;
+    __shared__ cx<R> fac[kCache ? N : 1];
 
     const Lanes<N, W> ln(threadIdx.x);
     const cx<R>* tw = static_cast<const cx<R>*>(A.tw);
@@ -313,6 +416,7 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
         if (l > g.l_tab) status = QT_TRAJ_LMAX;
         const bool has_gamma = g.gamma_hat != 0.0;
         const R dr = R(g.dr);
+        const double xmax = (double)(N - 1) * g.dr * (double)(N - 1) * g.dr;
         int cur = 0;
         while (status == QT_TRAJ_OK && step < end) {
             // lane-derived values are recomputed every step (see opaque_lane)
@@ -324,28 +428,33 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
             const double cc = (c == QT_SINGLET) ? 0.5 : 7.0 / 32.0;
             const R zr = R(-0.5 * g.dt * cc * g.kappa_hat * T3);
             const R zi = R(-0.5 * g.dt * cc * g.gamma_hat * T3);
-            const cx<R>* row = phase_row<R, N>(g, l, c);
+            const cx<R>* row = opaque(phase_row<R, N>(g, l, c));
+            // FP64 always takes the library functions
+            const bool fast = !kRenorm || (fabs(-0.5 * g.dt * cc * g.kappa_hat * T3) * xmax <= 0.5 &&
+                                           fabs(-0.5 * g.dt * cc * g.gamma_hat * T3) * xmax <= 0.78);
 
-            apply_half_step<R, N, W>(a, b, row, ls, dr, zr, zi, has_gamma);
             double n_in = 0.0;
-            if constexpr (kRenorm) n_in = block_sum<W>(sum_abs2<R, N, W>(a, b), red);
+            with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
+                const HalfStep<R, G, F> h{row, dr, zr, zi};
+                n_in = first_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac);
+            });
+            if constexpr (kRenorm) n_in = block_sum<W>(n_in, red);
             const cx<R>* tw_n = opaque(tw);
             dst1<R, N, W, true>(a, b, sines, ls, buf, wsum, tw_n, kin, kin_lo);
             dst1<R, N, W, false>(a, b, sines, ls, buf, wsum, opaque(tw_n), nullptr);
+            double x[2] = {0.0, 0.0};
+            with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
+                const HalfStep<R, G, F> h{opaque(row), dr, zr, zi};
+                second_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac, x[0], x[1]);
+            });
             if constexpr (kRenorm) {
-                // the block DST - kinetic - DST is unitary: restore its input
-                // norm, and take the norm of the second half-step in the same
-                // reduction
-                double x[2];
-                x[0] = sum_abs2<R, N, W>(a, b);
-                apply_half_step<R, N, W>(a, b, row, ls, dr, zr, zi, has_gamma);
-                x[1] = sum_abs2<R, N, W>(a, b);
+                // the block C DST kin DST C is unitary: restore the norm it
+                // received (D commutes with the scaling)
                 block_sum_vec<W, 2>(x, red);
                 add_scaled<R, N, W>(a, b, R(sqrt(n_in / x[0]) - 1.0));
                 norm = g.dr * x[1] * (n_in / x[0]);
             } else {
-                apply_half_step<R, N, W>(a, b, row, ls, dr, zr, zi, has_gamma);
-                norm = g.dr * block_sum<W>(sum_abs2<R, N, W>(a, b), red);
+                norm = g.dr * block_sum<W>(x[1], red);
             }
             step = n + 1;
             if (!g.do_jumps) continue;
