@@ -298,11 +298,59 @@ __device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R
 
 // ------------------------------------------------------- reductions -------
 
-template <class T>
-__device__ __forceinline__ T wave_sum(T x)
+// Cross-lane moves with the data-parallel-primitives (DPP) modifier: a VALU
+// move that reads another lane of the same row of 16 (or, for the two
+// broadcasts, the last lane of the previous row / of row 1), no LDS round
+// trip.  Lanes without a source, and rows left out by ROWS, read 0.
+enum : int {
+    kDppSwap1 = 0xB1,          // quad_perm [1,0,3,2]
+    kDppSwap2 = 0x4E,          // quad_perm [2,3,0,1]
+    kDppRowShr1 = 0x111,       // row_shr:n = 0x110 + n
+    kDppRowMirror = 0x140,
+    kDppRowHalfMirror = 0x141,
+    kDppBcast15 = 0x142,       // lane 15 of each row to the next row
+    kDppBcast31 = 0x143,       // lane 31 to rows 2 and 3
+};
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp(float x)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                                 ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp(double x)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of the wave, as a wave-uniform value.
+__device__ __forceinline__ double wave_sum(double x)
+{
+    x += dpp<kDppSwap1>(x);
+    x += dpp<kDppSwap2>(x);
+    x += dpp<kDppRowHalfMirror>(x);
+    x += dpp<kDppRowMirror>(x);          // every lane: its row's sum
+    x += dpp<kDppBcast15, 0xA>(x);       // rows 1, 3: rows 0+1, 2+3
+    x += dpp<kDppBcast31, 0xC>(x);       // row 3: all rows
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 63);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Inclusive prefix sum over the 64 lanes of the wave (lane order).
+template <class T>
+__device__ __forceinline__ T wave_inclusive_scan(T x)
+{
+    x += dpp<kDppRowShr1>(x);
+    x += dpp<kDppRowShr1 + 1>(x);
+    x += dpp<kDppRowShr1 + 3>(x);
+    x += dpp<kDppRowShr1 + 7>(x);        // scan within each row of 16
+    x += dpp<kDppBcast15, 0xA>(x);       // rows 1, 3 add the end of rows 0, 2
+    x += dpp<kDppBcast31, 0xC>(x);       // rows 2, 3 add the end of row 1
     return x;
 }
 
@@ -349,18 +397,11 @@ __device__ __forceinline__ double block_sum(double x, double* red)
 template <int W, class R>
 __device__ __forceinline__ cx<R> block_exclusive_scan(cx<R> x, cx<R>* wsum)
 {
-    const int lane = threadIdx.x & 63;
-    cx<R> inc = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        R yr = __shfl_up(inc.re, d, 64);
-        R yi = __shfl_up(inc.im, d, 64);
-        if (lane >= d) { inc.re += yr; inc.im += yi; }
-    }
+    cx<R> inc = mk(wave_inclusive_scan(x.re), wave_inclusive_scan(x.im));
     cx<R> exc = inc - x;
     if constexpr (W > 64) {
         const int wave = threadIdx.x >> 6;
-        if (lane == 63) wsum[wave] = inc;
+        if ((threadIdx.x & 63) == 63) wsum[wave] = inc;
         __syncthreads();
         cx<R> off = mk(R(0), R(0));
         for (int w = 0; w < wave; ++w) off = off + wsum[w];

@@ -438,23 +438,24 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
                 const HalfStep<R, G, F> h{row, dr, zr, zi};
                 n_in = first_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac);
             });
-            if constexpr (kRenorm) n_in = block_sum<W>(n_in, red);
             const cx<R>* tw_n = opaque(tw);
             dst1<R, N, W, true>(a, b, sines, ls, buf, wsum, tw_n, kin, kin_lo);
             dst1<R, N, W, false>(a, b, sines, ls, buf, wsum, opaque(tw_n), nullptr);
-            double x[2] = {0.0, 0.0};
+            // x: sum |D u|^2 after the first half-step (the norm the unitary
+            // block receives), sum |C u|^2 (what it returns), sum |D C u|^2
+            double x[3] = {n_in, 0.0, 0.0};
             with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
                 const HalfStep<R, G, F> h{opaque(row), dr, zr, zi};
-                second_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac, x[0], x[1]);
+                second_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac, x[1], x[2]);
             });
             if constexpr (kRenorm) {
                 // the block C DST kin DST C is unitary: restore the norm it
                 // received (D commutes with the scaling)
-                block_sum_vec<W, 2>(x, red);
-                add_scaled<R, N, W>(a, b, R(sqrt(n_in / x[0]) - 1.0));
-                norm = g.dr * x[1] * (n_in / x[0]);
+                block_sum_vec<W, 3>(x, red);
+                add_scaled<R, N, W>(a, b, R(sqrt(x[0] / x[1]) - 1.0));
+                norm = g.dr * x[2] * (x[0] / x[1]);
             } else {
-                norm = g.dr * block_sum<W>(x[1], red);
+                norm = g.dr * block_sum<W>(x[2], red);
             }
             step = n + 1;
             if (!g.do_jumps) continue;
