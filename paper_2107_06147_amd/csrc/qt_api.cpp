@@ -367,7 +367,7 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         const size_t N = h.phys.N;
         o[g].tau = off; off = align_up(off + h.tau.size() * 8);
         o[g].T = off; off = align_up(off + h.T.size() * 8);
-        o[g].kin = off; off = align_up(off + N * elem_bytes(prec) * (f32 ? 2 : 1));
+        o[g].kin = off; off = align_up(off + (size_t)N * 16);
         o[g].init = off; off = align_up(off + 2 * N * 8);
         o[g].basis = off; off = align_up(off + 6 * N * 8);
         o[g].Tn = off;
@@ -404,7 +404,6 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         d.tau = reinterpret_cast<const double*>(base + o[g].tau);
         d.Ttab = reinterpret_cast<const double*>(base + o[g].T);
         d.kin = base + o[g].kin;
-        d.kin_lo = f32 ? base + o[g].kin + (size_t)N * 8 : nullptr;
         d.init_psi = reinterpret_cast<const double*>(base + o[g].init);
         d.basis = reinterpret_cast<const double*>(base + o[g].basis);
         d.Tn = with_Tn ? reinterpret_cast<const double*>(base + o[g].Tn) : nullptr;
@@ -418,11 +417,14 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         std::memcpy(&blob[o[g].tau], h.tau.data(), h.tau.size() * 8);
         std::memcpy(&blob[o[g].T], h.T.data(), h.T.size() * 8);
         if (f32) {
-            // double-float kinetic factor: hi rounded, lo = the rest
+            // double-float kinetic factor per momentum: hi rounded, lo the rest
             float* k = reinterpret_cast<float*>(&blob[o[g].kin]);
-            for (int i = 0; i < 2 * N; ++i) {
-                k[i] = (float)h.kin[i];
-                k[2 * N + i] = (float)(h.kin[i] - (double)k[i]);
+            for (int m = 0; m < N; ++m) {
+                for (int c = 0; c < 2; ++c) {
+                    const double x = h.kin[2 * m + c];
+                    k[4 * m + c] = (float)x;
+                    k[4 * m + 2 + c] = (float)(x - (double)k[4 * m + c]);
+                }
             }
         } else {
             std::memcpy(&blob[o[g].kin], h.kin.data(), 2 * (size_t)N * 8);

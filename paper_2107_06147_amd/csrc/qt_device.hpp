@@ -84,6 +84,26 @@ __device__ __forceinline__ cx<R> ldg(const cx<R>* p, uint32_t i)
     z.im = v.y;
     return z;
 }
+// Kinetic factor of one momentum: FP32-bulk keeps it as a double-float
+// (hi + lo, both FP32) in one 16-byte element; FP64 as one complex.
+template <class R> struct Kin;
+template <> struct Kin<float> { cx<float> hi, lo; };
+template <> struct Kin<double> { cx<double> v; };
+__device__ __forceinline__ Kin<float> ldg(const Kin<float>* p, uint32_t i)
+{
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *(const QT_GLOBAL v4*)((const QT_GLOBAL char*)p + i * 16u);
+    Kin<float> k;
+    k.hi = mk(v.x, v.y);
+    k.lo = mk(v.z, v.w);
+    return k;
+}
+__device__ __forceinline__ Kin<double> ldg(const Kin<double>* p, uint32_t i)
+{
+    Kin<double> k;
+    k.v = ldg(reinterpret_cast<const cx<double>*>(p), i);
+    return k;
+}
 template <class R>
 __device__ __forceinline__ R ldg(const R* p, uint32_t i)
 {
@@ -246,53 +266,80 @@ struct Lanes {
     }
 };
 
+// Twiddle factors of pass p for this lane's butterflies (none for the first
+// pass, whose stride is 1).
+template <class R, int N, int W, int p>
+struct PassTwiddles {
+    using PL = Plan<N, W>;
+    static constexpr int RAD = PL::radix(p);
+    static constexpr int NS = PL::ns(p);
+    static constexpr int B = PL::P / RAD;
+    static constexpr int K = NS > 1 ? B * (RAD - 1) : 1;
+    cx<R> w[K];
+    __device__ __forceinline__ static int bfly(const Lanes<N, W>& ln, int q)
+    {
+        constexpr bool edge = (p == 0 || p == PL::NPASS - 1);
+        return edge ? (q == 0 ? ln.ja : ln.jb) : q * W + ln.t;
+    }
+    __device__ __forceinline__ void load(const Lanes<N, W>& ln, const cx<R>* tw)
+    {
+        if constexpr (NS > 1) {
+            sfor<0, B>([&](auto Q) QT_INL {
+                const int k = bfly(ln, Q) & (NS - 1);
+                sfor<1, RAD>([&](auto Rr) QT_INL {
+                    w[Q * (RAD - 1) + Rr - 1] = ldg(tw, Rr * k * (N / (NS * RAD)));
+                });
+            });
+        }
+    }
+};
+
 // One Stockham pass: twiddle, butterfly, and (unless last) exchange through
 // LDS into the input layout of the next pass.  Butterfly j of a pass with
 // stride NS reads x[j + r N/RAD] and writes y[(j/NS) NS RAD + j%NS + r NS].
+// The next pass's twiddles are loaded before the exchange, so that their
+// latency overlaps it.
 template <class R, int N, int W, int p>
 __device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf,
-                                           const cx<R>* __restrict__ tw)
+                                           const cx<R>* __restrict__ tw,
+                                           const PassTwiddles<R, N, W, p>& cur)
 {
     using PL = Plan<N, W>;
-    constexpr int RAD = PL::radix(p);
-    constexpr int NS = PL::ns(p);
-    constexpr int B = PL::P / RAD;
-    constexpr bool edge = (p == 0 || p == PL::NPASS - 1);
-    auto bfly = [&](int q) { return edge ? (q == 0 ? ln.ja : ln.jb) : q * W + ln.t; };
-    // this pass's twiddles are loaded here, not at the top of the transform
-    tw = opaque(tw);
+    using TW = PassTwiddles<R, N, W, p>;
+    constexpr int RAD = TW::RAD;
+    constexpr int NS = TW::NS;
+    constexpr int B = TW::B;
 
     sfor<0, B>([&](auto Q) QT_INL {
         constexpr int q = Q;
-        const int j = bfly(q);
         if constexpr (NS > 1) {
-            const int k = j & (NS - 1);
             sfor<1, RAD>([&](auto Rr) QT_INL {
                 constexpr int r = Rr;
-                v[q * RAD + r] = v[q * RAD + r] * ldg(tw, r * k * (N / (NS * RAD)));
+                v[q * RAD + r] = v[q * RAD + r] * cur.w[q * (RAD - 1) + r - 1];
             });
         }
         dft<RAD>(v + q * RAD);
     });
     if constexpr (p + 1 < PL::NPASS) {
+        PassTwiddles<R, N, W, p + 1> nxt;
+        nxt.load(ln, opaque(tw));
         sfor<0, B>([&](auto Q) QT_INL {
             constexpr int q = Q;
-            const int j = bfly(q);
+            const int j = TW::bfly(ln, q);
             cx<R>* dst = buf + pad((j / NS) * NS * RAD + (j & (NS - 1)));
             sfor<0, RAD>([&](auto Rr) QT_INL { dst[padc<Rr * NS>()] = v[q * RAD + Rr]; });
         });
         __syncthreads();
         constexpr int RAD2 = PL::radix(p + 1);
         constexpr int B2 = PL::P / RAD2;
-        constexpr bool edge2 = (p + 1 == PL::NPASS - 1);
         sfor<0, B2>([&](auto Q) QT_INL {
             constexpr int q = Q;
-            const int j = edge2 ? (q == 0 ? ln.ja : ln.jb) : q * W + ln.t;
+            const int j = PassTwiddles<R, N, W, p + 1>::bfly(ln, q);
             const cx<R>* src = buf + pad(j);
             sfor<0, RAD2>([&](auto Rr) QT_INL { v[q * RAD2 + Rr] = src[padc<Rr * (N / RAD2)>()]; });
         });
         __syncthreads();
-        fft_passes<R, N, W, p + 1>(v, ln, buf, tw);
+        fft_passes<R, N, W, p + 1>(v, ln, buf, tw, nxt);
     }
 }
 
@@ -410,6 +457,19 @@ __device__ __forceinline__ cx<R> block_exclusive_scan(cx<R> x, cx<R>* wsum)
     return exc;
 }
 
+// sin(pi m/N) at the points of the mirror layout: sn[r] for a[r], sn[R1 + r]
+// for b[r] (the same for both transforms of a step).
+template <class R, int N, int W>
+__device__ __forceinline__ void load_sines(R* sn, const R* sines, const Lanes<N, W>& ln)
+{
+    constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
+    sines = opaque(sines);
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        sn[Rr] = ldg(sines, ln.ja + Rr * T);
+        sn[R1 + Rr] = ldg(sines, ln.jb + Rr * T);
+    });
+}
+
 // ------------------------------------------------------------- DST-I ------
 //
 // F_k = sum_{m=1}^{N-1} x_m sin(pi m k / N) on complex data with one complex
@@ -419,14 +479,14 @@ __device__ __forceinline__ cx<R> block_exclusive_scan(cx<R> x, cx<R>* wsum)
 //   F_{2k}   = (i/2) (Y_k - Y_{N-k}),
 //   D_k      = (Y_k + Y_{N-k})/2 = F_{2k+1} - F_{2k-1},
 //   F_{2k+1} = sum_{q=0}^{k} D_q - Y_0/2.
-// On entry a/b hold x in the mirror layout, sa/sb the matching sin(pi m/N).
-// On exit a/b hold F (times kin[m] if kin != nullptr) in the same layout.
+// On entry a/b hold x in the mirror layout and sn the matching sin(pi m/N)
+// (sn[r] for a[r], sn[R1 + r] for b[r]; see load_sines).  On exit a/b hold
+// F (times the kinetic factor of each output if KIN) in the same layout.
 template <class R, int N, int W, bool KIN>
-__device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* __restrict__ sines,
+__device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* sn,
                                      const Lanes<N, W>& ln_in, cx<R>* buf, cx<R>* wsum,
                                      const cx<R>* __restrict__ tw,
-                                     const cx<R>* __restrict__ kin,
-                                     const cx<R>* __restrict__ kin_lo = nullptr)
+                                     const Kin<R>* __restrict__ kin)
 {
     using PL = Plan<N, W>;
     constexpr int R1 = PL::R1;
@@ -435,27 +495,27 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* __restrict__ s
     const bool lane0 = ln.t == 0;
     cx<R> v[PL::P];
     const R half = R(0.5);
-    sines = opaque(sines);
     // pre-processing
     sfor<0, R1>([&](auto Rr) QT_INL {
         constexpr int r = Rr;
         cx<R> xa = a[r];
         cx<R> ma = pick(lane0, a[(R1 - r) % R1], b[R1 - 1 - r]);
-        v[r] = scale(xa + ma, ldg(sines, ln.ja + r * T)) + scale(xa - ma, half);
+        v[r] = scale(xa + ma, sn[r]) + scale(xa - ma, half);
         cx<R> xb = b[r];
         cx<R> mb = pick(lane0, b[R1 - 1 - r], a[R1 - 1 - r]);
-        v[R1 + r] = scale(xb + mb, ldg(sines, ln.jb + r * T)) + scale(xb - mb, half);
+        v[R1 + r] = scale(xb + mb, sn[R1 + r]) + scale(xb - mb, half);
     });
-    fft_passes<R, N, W, 0>(v, ln, buf, tw);
-    // F * kin, with the low part of a double-float kinetic factor in FP32
-    constexpr bool LO = std::is_same<R, float>::value;
-    if constexpr (KIN) {
-        kin = opaque(kin);
-        if constexpr (LO) kin_lo = opaque(kin_lo);
+    {
+        PassTwiddles<R, N, W, 0> none;
+        fft_passes<R, N, W, 0>(v, ln, buf, tw, none);
     }
+    // F * kin (FP32: hi and lo parts of the double-float factor)
+    if constexpr (KIN) kin = opaque(kin);
     auto kmul = [&](cx<R> F, int m) QT_INL {
-        cx<R> G = F * ldg(kin, m);
-        if constexpr (LO) G = G + F * ldg(kin_lo, m);
+        const Kin<R> k = ldg(kin, m);
+        cx<R> G;
+        if constexpr (std::is_same<R, float>::value) G = F * k.hi + F * k.lo;
+        else G = F * k.v;
         return G;
     };
     // post-processing: pairs (k, N-k), even outputs and differences D_k

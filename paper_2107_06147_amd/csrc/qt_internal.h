@@ -25,8 +25,8 @@ struct GroupDesc {
     uint64_t seed, traj_id0, traj_id_stride;
     const double* tau;
     const double* Ttab;
-    const void*   kin;        // N complex, precision of the kernel, 2/N folded in
-    const void*   kin_lo;     // FP32 form: N complex low parts (kin - hi), else null
+    const void*   kin;        // N kinetic factors (2/N folded in), 16 bytes each:
+                              // FP64 complex, or FP32 hi.re hi.im lo.re lo.im
     const double* init_psi;   // 2N doubles (re, im)
     const double* basis;      // 6N doubles
     const double* Tn;         // per-step temperature (plain form only)

@@ -167,9 +167,9 @@ struct HalfStep {
     {
         return FAST ? expm1_small(zr * x2) : qexpm1(zr * x2);
     }
-    __device__ __forceinline__ cx<R> phase(int m, R x2) const
+    __device__ __forceinline__ cx<R> static_phase(int m) const { return ldg(row, m); }
+    __device__ __forceinline__ cx<R> phase(cx<R> p, R x2) const
     {
-        const cx<R> p = ldg(row, m);
         if constexpr (GAMMA) {
             R s, c;
             if constexpr (FAST) sincos_small(zi * x2, &s, &c);
@@ -191,11 +191,17 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const HalfStep<
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
     double acc = 0.0;
     cx<R>* mine = fac + ln.t;
+    // static phases first: every load in flight at once
+    cx<R> pr[2 * R1];
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        pr[Rr] = h.static_phase(ln.ja + Rr * T);
+        pr[R1 + Rr] = h.static_phase(ln.jb + Rr * T);
+    });
     auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
         const R x2 = h.r2(m);
         const cx<R> w = u + scale(u, h.em1(x2));
         if constexpr (SUM) acc += abs2d(w);
-        const cx<R> C = h.phase(m, x2);
+        const cx<R> C = h.phase(pr[E], x2);
         if constexpr (CACHE) mine[E * W] = C;
         u = C * w;
     };
@@ -220,7 +226,7 @@ __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const HalfStep<R
         const R x2 = h.r2(m);
         cx<R> C;
         if constexpr (CACHE) C = mine[E * W];
-        else C = h.phase(m, x2);
+        else C = h.phase(h.static_phase(m), x2);
         const cx<R> w = C * u;
         if constexpr (SUM0) x0 += abs2d(w);
         u = w + scale(w, h.em1(x2));
@@ -374,8 +380,7 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
         const int64_t idx = uniform(A.item_index[item]);
         const uint64_t stride = g.traj_id_stride ? g.traj_id_stride : 1u;
         const uint64_t traj_id = g.traj_id0 + (uint64_t)idx * stride;
-        const cx<R>* kin = static_cast<const cx<R>*>(g.kin);
-        const cx<R>* kin_lo = static_cast<const cx<R>*>(g.kin_lo);
+        const Kin<R>* kin = static_cast<const Kin<R>*>(g.kin);
 
         cx<R> a[R1], b[R1];
         int l, c, n_jumps, status;
@@ -433,14 +438,16 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
             const bool fast = !kRenorm || (fabs(-0.5 * g.dt * cc * g.kappa_hat * T3) * xmax <= 0.5 &&
                                            fabs(-0.5 * g.dt * cc * g.gamma_hat * T3) * xmax <= 0.78);
 
+            R sn[Plan<N, W>::P];
+            load_sines<R, N, W>(sn, sines, ls);
             double n_in = 0.0;
             with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
                 const HalfStep<R, G, F> h{row, dr, zr, zi};
                 n_in = first_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac);
             });
             const cx<R>* tw_n = opaque(tw);
-            dst1<R, N, W, true>(a, b, sines, ls, buf, wsum, tw_n, kin, kin_lo);
-            dst1<R, N, W, false>(a, b, sines, ls, buf, wsum, opaque(tw_n), nullptr);
+            dst1<R, N, W, true>(a, b, sn, ls, buf, wsum, tw_n, kin);
+            dst1<R, N, W, false>(a, b, sn, ls, buf, wsum, opaque(tw_n), nullptr);
             // x: sum |D u|^2 after the first half-step (the norm the unitary
             // block receives), sum |C u|^2 (what it returns), sum |D C u|^2
             double x[3] = {n_in, 0.0, 0.0};
@@ -677,7 +684,9 @@ __global__ __launch_bounds__(W) void plain_dst_kernel(double* psi, const TrajSta
         a[Rr] = u[ln.ja + Rr * T];
         b[Rr] = u[ln.jb + Rr * T];
     });
-    dst1<double, N, W, false>(a, b, sines, ln, buf, wsum, static_cast<const cx<double>*>(twv), nullptr);
+    double sn[Plan<N, W>::P];
+    load_sines<double, N, W>(sn, sines, ln);
+    dst1<double, N, W, false>(a, b, sn, ln, buf, wsum, static_cast<const cx<double>*>(twv), nullptr);
     sfor<0, R1>([&](auto Rr) QT_INL {
         u[ln.ja + Rr * T] = a[Rr];
         u[ln.jb + Rr * T] = b[Rr];
