@@ -509,39 +509,34 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* sn,
         PassTwiddles<R, N, W, 0> none;
         fft_passes<R, N, W, 0>(v, ln, buf, tw, none);
     }
-    // F * kin (FP32: hi and lo parts of the double-float factor)
-    if constexpr (KIN) kin = opaque(kin);
-    auto kmul = [&](cx<R> F, int m) QT_INL {
-        const Kin<R> k = ldg(kin, m);
-        cx<R> G;
-        if constexpr (std::is_same<R, float>::value) G = F * k.hi + F * k.lo;
-        else G = F * k.v;
-        return G;
-    };
     // post-processing: pairs (k, N-k), even outputs and differences D_k
     sfor<0, R1 / 2>([&](auto Rr) QT_INL {
         constexpr int r = Rr;
         {
             cx<R> y = v[r];
             cx<R> yp = pick(lane0, v[(R1 - r) % R1], v[R1 + R1 - 1 - r]);
-            const int k = ln.ja + r * T;
-            cx<R> F = mul_ihalf(y - yp);
-            if constexpr (KIN) F = kmul(F, 2 * k);
             cx<R>* dst = buf + pad(2 * ln.ja);
-            dst[padc<2 * r * T>()] = F;
+            dst[padc<2 * r * T>()] = mul_ihalf(y - yp);
             dst[padc<2 * r * T>() + 1] = scale(y + yp, half);
         }
         {
             cx<R> y = v[R1 + r];
             cx<R> yp = pick(lane0, v[R1 + R1 - 1 - r], v[R1 - 1 - r]);
-            const int k = ln.jb + r * T;
-            cx<R> F = mul_ihalf(y - yp);
-            if constexpr (KIN) F = kmul(F, 2 * k);
             cx<R>* dst = buf + pad(2 * ln.jb);
-            dst[padc<2 * r * T>()] = F;
+            dst[padc<2 * r * T>()] = mul_ihalf(y - yp);
             dst[padc<2 * r * T>() + 1] = scale(y + yp, half);
         }
     });
+    // kinetic factors of the outputs this lane ends up holding (mirror
+    // layout), loaded here so that the exchanges below hide their latency
+    Kin<R> kk[KIN ? PL::P : 1];
+    if constexpr (KIN) {
+        kin = opaque(kin);
+        sfor<0, R1>([&](auto Rr) QT_INL {
+            kk[Rr] = ldg(kin, ln.ja + Rr * T);
+            kk[R1 + Rr] = ldg(kin, ln.jb + Rr * T);
+        });
+    }
     __syncthreads();
     // prefix sum of D_k over k = 0..N/2-1: contiguous chunks per lane
     constexpr int CH = N / (2 * W);
@@ -554,19 +549,23 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* sn,
         pre[I] = run;
     });
     const cx<R> off = block_exclusive_scan<W>(run, wsum) - scale(d0, half);
-    sfor<0, CH>([&](auto I) QT_INL {
-        const int k = ln.t * CH + I;
-        cx<R> F = pre[I] + off;
-        if constexpr (KIN) F = kmul(F, 2 * k + 1);
-        chunk[padc<2 * I + 1>()] = F;
-    });
+    sfor<0, CH>([&](auto I) QT_INL { chunk[padc<2 * I + 1>()] = pre[I] + off; });
     __syncthreads();
+    // F * kin (FP32: hi and lo parts of the double-float factor)
+    auto kmul = [&](cx<R> F, const Kin<R>& k) QT_INL {
+        if constexpr (std::is_same<R, float>::value) return F * k.hi + F * k.lo;
+        else return F * k.v;
+    };
     {
         const cx<R>* sa = buf + pad(ln.ja);
         const cx<R>* sb = buf + pad(ln.jb);
         sfor<0, R1>([&](auto Rr) QT_INL {
             a[Rr] = sa[padc<Rr * T>()];
             b[Rr] = sb[padc<Rr * T>()];
+            if constexpr (KIN) {
+                a[Rr] = kmul(a[Rr], kk[Rr]);
+                b[Rr] = kmul(b[Rr], kk[R1 + Rr]);
+            }
         });
     }
     __syncthreads();

@@ -183,10 +183,11 @@ struct HalfStep {
 
 // First half-step: u <- C D u.  Returns this lane's part of sum |D u|^2 (the
 // norm the unitary block receives) when SUM; stores C_m in `fac` (this
-// lane's slots, no other lane reads them) when CACHE.
+// lane's slots, no other lane reads them) when CACHE, and D_m - 1 in dm
+// (registers, for the second half-step).
 template <class R, int N, int W, bool GAMMA, bool FAST, bool CACHE, bool SUM>
 __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const HalfStep<R, GAMMA, FAST>& h,
-                                             const Lanes<N, W>& ln, cx<R>* fac)
+                                             const Lanes<N, W>& ln, cx<R>* fac, R* dm)
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
     double acc = 0.0;
@@ -199,7 +200,8 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const HalfStep<
     });
     auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
         const R x2 = h.r2(m);
-        const cx<R> w = u + scale(u, h.em1(x2));
+        dm[E] = h.em1(x2);
+        const cx<R> w = u + scale(u, dm[E]);
         if constexpr (SUM) acc += abs2d(w);
         const cx<R> C = h.phase(pr[E], x2);
         if constexpr (CACHE) mine[E * W] = C;
@@ -217,19 +219,18 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const HalfStep<
 // SUM0) and sum |D C u|^2 to x1.
 template <class R, int N, int W, bool GAMMA, bool FAST, bool CACHE, bool SUM0>
 __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const HalfStep<R, GAMMA, FAST>& h,
-                                            const Lanes<N, W>& ln, const cx<R>* fac, double& x0,
-                                            double& x1)
+                                            const Lanes<N, W>& ln, const cx<R>* fac, const R* dm,
+                                            double& x0, double& x1)
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
     const cx<R>* mine = fac + ln.t;
     auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
-        const R x2 = h.r2(m);
         cx<R> C;
         if constexpr (CACHE) C = mine[E * W];
-        else C = h.phase(h.static_phase(m), x2);
+        else C = h.phase(h.static_phase(m), h.r2(m));
         const cx<R> w = C * u;
         if constexpr (SUM0) x0 += abs2d(w);
-        u = w + scale(w, h.em1(x2));
+        u = w + scale(w, dm[E]);
         x1 += abs2d(u);
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
@@ -440,10 +441,11 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
 
             R sn[Plan<N, W>::P];
             load_sines<R, N, W>(sn, sines, ls);
+            R dm[Plan<N, W>::P];
             double n_in = 0.0;
             with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
                 const HalfStep<R, G, F> h{row, dr, zr, zi};
-                n_in = first_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac);
+                n_in = first_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac, dm);
             });
             const cx<R>* tw_n = opaque(tw);
             dst1<R, N, W, true>(a, b, sn, ls, buf, wsum, tw_n, kin);
@@ -453,7 +455,7 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
             double x[3] = {n_in, 0.0, 0.0};
             with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
                 const HalfStep<R, G, F> h{opaque(row), dr, zr, zi};
-                second_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac, x[1], x[2]);
+                second_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac, dm, x[1], x[2]);
             });
             if constexpr (kRenorm) {
                 // the block C DST kin DST C is unitary: restore the norm it
