@@ -156,13 +156,134 @@ static void normalise(std::vector<double>& u, int N, double dr, bool complex_pai
     for (double& v : u) v *= f;
 }
 
+// Process-wide cache of host tables keyed by the parameters they depend on.
+// Entries live as long as some batch holds them.
+template <class T>
+class TableCache {
+public:
+    template <class Make>
+    std::shared_ptr<const T> get(const std::vector<double>& key, Make make)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = m_.find(key);
+        if (it != m_.end()) {
+            if (auto sp = it->second.lock()) return sp;
+        }
+        if (m_.size() > 256) {
+            for (auto i = m_.begin(); i != m_.end();) i = i->second.expired() ? m_.erase(i) : std::next(i);
+        }
+        std::shared_ptr<const T> sp = make();
+        if (sp) m_[key] = sp;
+        return sp;
+    }
+
+private:
+    std::mutex mu_;
+    std::map<std::vector<double>, std::weak_ptr<const T>> m_;
+};
+
+static const int kBasisN[6] = {1, 2, 2, 3, 3, 3}, kBasisL[6] = {0, 0, 1, 0, 1, 2};
+
+// kinetic factors (2/N) exp(-i E_k dt); 2/N is the scale of two
+// unnormalised sine transforms
+static std::shared_ptr<const std::vector<double>> kinetic_table(const qt_physics* p)
+{
+    static TableCache<std::vector<double>> cache;
+    const int N = p->N;
+    const int off = (p->flags & QT_FLAG_KINETIC_OFF) ? 1 : 0;
+    const std::vector<double> key{(double)N, p->L, p->dt, p->mass, (double)p->deriv_type, (double)off};
+    return cache.get(key, [&] {
+        const double dr = p->L / N;
+        auto t = std::make_shared<std::vector<double>>(2 * (size_t)N, 0.0);
+        for (int k = 1; k < N; ++k) {
+            double re = 1.0, im = 0.0;
+            if (!off) {
+                const double pk = kPi * k / p->L;
+                const double E = p->deriv_type == 1 ? 2.0 * (1.0 - std::cos(pk * dr)) / (p->mass * dr * dr)
+                                                    : pk * pk / p->mass;
+                re = std::cos(E * p->dt);
+                im = -std::sin(E * p->dt);
+            }
+            (*t)[2 * k] = (2.0 / N) * re;
+            (*t)[2 * k + 1] = (2.0 / N) * im;
+        }
+        return std::shared_ptr<const std::vector<double>>(t);
+    });
+}
+
+// Coulomb basis 1S, 2S, 1P, 3S, 2P, 1D (zero when alpha_s = 0)
+static std::shared_ptr<const std::vector<double>> basis_table(const qt_physics* p)
+{
+    static TableCache<std::vector<double>> cache;
+    const int N = p->N;
+    const std::vector<double> key{(double)N, p->L, p->mass, p->alpha_s};
+    return cache.get(key, [&] {
+        const double dr = p->L / N;
+        auto t = std::make_shared<std::vector<double>>(6 * (size_t)N, 0.0);
+        if (p->alpha_s > 0) {
+            const double a0 = 2.0 / (p->mass * (4.0 / 3.0) * p->alpha_s);
+            for (int q = 0; q < 6; ++q) {
+                std::vector<double> u(N, 0.0);
+                for (int j = 1; j < N; ++j) u[j] = hydrogen(kBasisN[q], kBasisL[q], a0, j * dr);
+                normalise(u, N, dr, false);
+                std::copy(u.begin(), u.end(), t->begin() + (size_t)q * N);
+            }
+        }
+        return std::shared_ptr<const std::vector<double>>(t);
+    });
+}
+
+// Initial state and its overlaps; null if its norm is zero or not finite.
+static std::shared_ptr<const InitTable> make_init(const qt_physics* p, const qt_init* in,
+                                                  const std::vector<double>& basis)
+{
+    const int N = p->N;
+    const double dr = p->L / N;
+    auto t = std::make_shared<InitTable>();
+    std::vector<double>& psi = t->psi;
+    psi.assign(2 * (size_t)N, 0.0);
+    if (in->kind == QT_INIT_COULOMB) {
+        const double a0 = 2.0 / (p->mass * (4.0 / 3.0) * p->alpha_s);
+        for (int j = 1; j < N; ++j) psi[2 * j] = hydrogen(in->n, in->l, a0, j * dr);
+    } else if (in->kind == QT_INIT_GAUSSIAN) {
+        for (int j = 1; j < N; ++j) {
+            const double r = j * dr;
+            psi[2 * j] = std::pow(r, (double)(in->l + 1)) * std::exp(-r * r / (2.0 * in->width * in->width));
+        }
+    } else {
+        for (int j = 1; j < N; ++j) {
+            psi[2 * j] = in->u_re[j];
+            psi[2 * j + 1] = in->u_im ? in->u_im[j] : 0.0;
+        }
+    }
+    double s = 0.0;
+    for (int j = 1; j < N; ++j) s += psi[2 * j] * psi[2 * j] + psi[2 * j + 1] * psi[2 * j + 1];
+    if (!(s > 0) || !std::isfinite(s)) return nullptr;
+    normalise(psi, N, dr, true);
+
+    // initial overlaps |<b|u>|^2/<u|u> (singlet of matching l only)
+    double nrm = 0.0;
+    for (int j = 1; j < N; ++j) nrm += psi[2 * j] * psi[2 * j] + psi[2 * j + 1] * psi[2 * j + 1];
+    for (int q = 0; q < 6; ++q) {
+        t->overlap[q] = 0.0;
+        if (in->color != QT_SINGLET || in->l != kBasisL[q] || !(p->alpha_s > 0)) continue;
+        double ar = 0.0, ai = 0.0;
+        for (int j = 1; j < N; ++j) {
+            ar += basis[(size_t)q * N + j] * psi[2 * j];
+            ai += basis[(size_t)q * N + j] * psi[2 * j + 1];
+        }
+        ar *= dr;
+        ai *= dr;
+        t->overlap[q] = (ar * ar + ai * ai) / (dr * nrm);
+    }
+    return t;
+}
+
 qt_status prepare(const qt_physics* p, const qt_ttable* tt, const qt_init* in, const qt_batch* b,
                   HostBatch* hb)
 {
     qt_status st = validate(p, tt, in, b);
     if (st != QT_OK) return st;
-    const int N = p->N;
-    const double dr = p->L / N;
     hb->phys = *p;
     hb->batch = *b;
     hb->init_l = in->l;
@@ -172,75 +293,17 @@ qt_status prepare(const qt_physics* p, const qt_ttable* tt, const qt_init* in, c
     hb->tau_start = tt->tau_start;
     hb->T_final = tt->T_final;
     hb->n_steps = count_steps(*p, *tt);
-
-    // kinetic factors (2/N) exp(-i E_k dt); 2/N is the scale of two
-    // unnormalised sine transforms
-    hb->kin.assign(2 * (size_t)N, 0.0);
-    for (int k = 1; k < N; ++k) {
-        double re = 1.0, im = 0.0;
-        if (!(p->flags & QT_FLAG_KINETIC_OFF)) {
-            const double pk = kPi * k / p->L;
-            const double E = p->deriv_type == 1 ? 2.0 * (1.0 - std::cos(pk * dr)) / (p->mass * dr * dr)
-                                                : pk * pk / p->mass;
-            re = std::cos(E * p->dt);
-            im = -std::sin(E * p->dt);
-        }
-        hb->kin[2 * k] = (2.0 / N) * re;
-        hb->kin[2 * k + 1] = (2.0 / N) * im;
-    }
-
-    // Coulomb basis 1S, 2S, 1P, 3S, 2P, 1D
-    static const int bn[6] = {1, 2, 2, 3, 3, 3}, bl[6] = {0, 0, 1, 0, 1, 2};
-    hb->basis.assign(6 * (size_t)N, 0.0);
-    if (p->alpha_s > 0) {
-        const double a0 = 2.0 / (p->mass * (4.0 / 3.0) * p->alpha_s);
-        for (int q = 0; q < 6; ++q) {
-            std::vector<double> u(N, 0.0);
-            for (int j = 1; j < N; ++j) u[j] = hydrogen(bn[q], bl[q], a0, j * dr);
-            normalise(u, N, dr, false);
-            std::copy(u.begin(), u.end(), hb->basis.begin() + (size_t)q * N);
-        }
-    }
-
-    // initial state
-    hb->init_psi.assign(2 * (size_t)N, 0.0);
-    if (in->kind == QT_INIT_COULOMB) {
-        const double a0 = 2.0 / (p->mass * (4.0 / 3.0) * p->alpha_s);
-        for (int j = 1; j < N; ++j) hb->init_psi[2 * j] = hydrogen(in->n, in->l, a0, j * dr);
-    } else if (in->kind == QT_INIT_GAUSSIAN) {
-        for (int j = 1; j < N; ++j) {
-            const double r = j * dr;
-            hb->init_psi[2 * j] = std::pow(r, (double)(in->l + 1)) *
-                                  std::exp(-r * r / (2.0 * in->width * in->width));
-        }
+    hb->kin = kinetic_table(p);
+    hb->basis = basis_table(p);
+    if (in->kind == QT_INIT_ARRAY) {
+        hb->init = make_init(p, in, *hb->basis);
     } else {
-        for (int j = 1; j < N; ++j) {
-            hb->init_psi[2 * j] = in->u_re[j];
-            hb->init_psi[2 * j + 1] = in->u_im ? in->u_im[j] : 0.0;
-        }
+        static TableCache<InitTable> cache;
+        const std::vector<double> key{(double)p->N, p->L, p->mass, p->alpha_s, (double)in->kind,
+                                      (double)in->n, (double)in->l, (double)in->color, in->width};
+        hb->init = cache.get(key, [&] { return make_init(p, in, *hb->basis); });
     }
-    double s = 0.0;
-    for (int j = 1; j < N; ++j)
-        s += hb->init_psi[2 * j] * hb->init_psi[2 * j] + hb->init_psi[2 * j + 1] * hb->init_psi[2 * j + 1];
-    if (!(s > 0) || !std::isfinite(s)) return fail(QT_EINVAL, "initial state has zero or non-finite norm");
-    normalise(hb->init_psi, N, dr, true);
-
-    // initial overlaps |<b|u>|^2/<u|u> (singlet of matching l only)
-    double nrm = 0.0;
-    for (int j = 1; j < N; ++j)
-        nrm += hb->init_psi[2 * j] * hb->init_psi[2 * j] + hb->init_psi[2 * j + 1] * hb->init_psi[2 * j + 1];
-    for (int q = 0; q < 6; ++q) {
-        hb->init_overlap[q] = 0.0;
-        if (in->color != QT_SINGLET || in->l != bl[q] || !(p->alpha_s > 0)) continue;
-        double ar = 0.0, ai = 0.0;
-        for (int j = 1; j < N; ++j) {
-            ar += hb->basis[(size_t)q * N + j] * hb->init_psi[2 * j];
-            ai += hb->basis[(size_t)q * N + j] * hb->init_psi[2 * j + 1];
-        }
-        ar *= dr;
-        ai *= dr;
-        hb->init_overlap[q] = (ar * ar + ai * ai) / (dr * nrm);
-    }
+    if (!hb->init) return fail(QT_EINVAL, "initial state has zero or non-finite norm");
     return QT_OK;
 }
 
@@ -360,16 +423,29 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
     const bool f32 = prec == QT_FP32_BULK;
     const size_t ng = hb.size();
     size_t off = align_up(ng * sizeof(GroupDesc));
-    struct Offs { size_t tau, T, kin, init, basis, Tn; };
+    // the N-sized tables go in once however many groups share them
+    struct Offs { size_t tau, T, kin, init, basis, Tn; bool own_kin, own_init, own_basis; };
     std::vector<Offs> o(ng);
+    std::map<const void*, size_t> seen;
+    auto place = [&](const void* key, size_t bytes, size_t* at) {
+        auto it = seen.find(key);
+        if (it != seen.end()) {
+            *at = it->second;
+            return false;
+        }
+        *at = off;
+        off = align_up(off + bytes);
+        seen[key] = *at;
+        return true;
+    };
     for (size_t g = 0; g < ng; ++g) {
         const HostBatch& h = *hb[g];
         const size_t N = h.phys.N;
         o[g].tau = off; off = align_up(off + h.tau.size() * 8);
         o[g].T = off; off = align_up(off + h.T.size() * 8);
-        o[g].kin = off; off = align_up(off + (size_t)N * 16);
-        o[g].init = off; off = align_up(off + 2 * N * 8);
-        o[g].basis = off; off = align_up(off + 6 * N * 8);
+        o[g].own_kin = place(h.kin.get(), N * 16, &o[g].kin);
+        o[g].own_init = place(h.init.get(), 2 * N * 8, &o[g].init);
+        o[g].own_basis = place(h.basis.get(), 6 * N * 8, &o[g].basis);
         o[g].Tn = off;
         if (with_Tn) off = align_up(off + (size_t)std::max<int64_t>(h.n_steps, 1) * 8);
     }
@@ -409,28 +485,28 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         d.Tn = with_Tn ? reinterpret_cast<const double*>(base + o[g].Tn) : nullptr;
         d.phase = phase[g];
         d.l_tab = kLTab;
-        for (int q = 0; q < 6; ++q) d.init_overlap[q] = h.init_overlap[q];
+        for (int q = 0; q < 6; ++q) d.init_overlap[q] = h.init->overlap[q];
         d.out = outs[g];
         d.st_psi = nullptr;
         d.st = nullptr;
         dg->host[g] = d;
         std::memcpy(&blob[o[g].tau], h.tau.data(), h.tau.size() * 8);
         std::memcpy(&blob[o[g].T], h.T.data(), h.T.size() * 8);
-        if (f32) {
+        if (o[g].own_kin && f32) {
             // double-float kinetic factor per momentum: hi rounded, lo the rest
             float* k = reinterpret_cast<float*>(&blob[o[g].kin]);
             for (int m = 0; m < N; ++m) {
                 for (int c = 0; c < 2; ++c) {
-                    const double x = h.kin[2 * m + c];
+                    const double x = (*h.kin)[2 * m + c];
                     k[4 * m + c] = (float)x;
                     k[4 * m + 2 + c] = (float)(x - (double)k[4 * m + c]);
                 }
             }
-        } else {
-            std::memcpy(&blob[o[g].kin], h.kin.data(), 2 * (size_t)N * 8);
+        } else if (o[g].own_kin) {
+            std::memcpy(&blob[o[g].kin], h.kin->data(), 2 * (size_t)N * 8);
         }
-        std::memcpy(&blob[o[g].init], h.init_psi.data(), 2 * (size_t)N * 8);
-        std::memcpy(&blob[o[g].basis], h.basis.data(), 6 * (size_t)N * 8);
+        if (o[g].own_init) std::memcpy(&blob[o[g].init], h.init->psi.data(), 2 * (size_t)N * 8);
+        if (o[g].own_basis) std::memcpy(&blob[o[g].basis], h.basis->data(), 6 * (size_t)N * 8);
         if (with_Tn) {
             double* Tn = reinterpret_cast<double*>(&blob[o[g].Tn]);
             for (int64_t n = 0; n < h.n_steps; ++n)

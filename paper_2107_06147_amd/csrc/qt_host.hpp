@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -39,7 +40,16 @@ qt_status fail(qt_status s, const char* fmt, ...);
 
 int elem_bytes(int prec);     // bytes of one complex value of the precision
 
+// Initial state (2N, normalised) and its overlaps with the six Coulomb
+// states.
+struct InitTable {
+    std::vector<double> psi;
+    double overlap[6] = {0, 0, 0, 0, 0, 0};
+};
+
 // Host copy of one batch's setup (everything the device needs, in FP64).
+// The N-sized tables are shared between all batches with the same
+// parameters (see prepare), and uploaded once per launch.
 struct HostBatch {
     qt_physics phys;
     qt_batch batch;
@@ -47,10 +57,9 @@ struct HostBatch {
     int64_t n_steps = 0;
     std::vector<double> tau, T;
     double tau_start = 0, T_final = 0;
-    std::vector<double> kin;        // 2N: (2/N) exp(-i E_k dt)
-    std::vector<double> init_psi;   // 2N
-    std::vector<double> basis;      // 6N
-    double init_overlap[6] = {0, 0, 0, 0, 0, 0};
+    std::shared_ptr<const std::vector<double>> kin;     // 2N: (2/N) exp(-i E_k dt)
+    std::shared_ptr<const std::vector<double>> basis;   // 6N
+    std::shared_ptr<const InitTable> init;
 };
 
 qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in,

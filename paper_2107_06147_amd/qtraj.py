@@ -198,10 +198,13 @@ def alloc_results(n, N, want_psi, device="cuda"):
     return out, results_struct(out)
 
 
-def results_struct(out):
+def results_struct(out, row=0):
+    """qt_results of the tensors in `out`, starting at trajectory `row`."""
     def p(name, typ):
         t = out.get(name)
-        return C.cast(C.c_void_p(t.data_ptr()), typ) if t is not None else None
+        if t is None:
+            return None
+        return C.cast(C.c_void_p(t.data_ptr() + row * t.stride(0) * t.element_size()), typ)
     return qt_results(p("norm", _D), p("first_r", _D), p("overlap", _D), p("survival", _D),
                       p("mean_r", _D), p("l", _I32), p("color", _I32), p("n_jumps", _I32),
                       p("status", _I32), p("steps_done", _I64), p("min_gap", _D), p("psi", _D))
@@ -301,8 +304,10 @@ def run(ctx, cfg, precision=QT_FP64, form=QT_FORM_FUSED, want_psi=False, n_traj=
     return out
 
 
-def run_many(ctx, cfgs, precision=QT_FP32_BULK, want_psi=False, stream=None):
-    """qt_run_many over a list of config dicts; returns one output dict each."""
+def run_many(ctx, cfgs, precision=QT_FP32_BULK, want_psi=False, stream=None, flat=False):
+    """qt_run_many over a list of config dicts; returns one output dict each,
+    or with flat=True (no wave functions) one dict holding every config's
+    trajectories one after the other, in config order."""
     keep = []
     k = len(cfgs)
     P = (qt_physics * k)()
@@ -311,16 +316,26 @@ def run_many(ctx, cfgs, precision=QT_FP32_BULK, want_psi=False, stream=None):
     B = (qt_batch * k)()
     RS = (qt_results * k)()
     outs = []
+    if flat:
+        if want_psi:
+            raise ValueError("flat results hold no wave functions")
+        total = sum(int(c["n_traj"]) for c in cfgs)
+        flat_out, _ = alloc_results(total, 0, False)
+    row = 0
     for i, cfg in enumerate(cfgs):
-        o, r = alloc_results(int(cfg["n_traj"]), int(cfg["N"]), want_psi)
-        outs.append(o)
+        if flat:
+            r = results_struct(flat_out, row)
+            row += int(cfg["n_traj"])
+        else:
+            o, r = alloc_results(int(cfg["n_traj"]), int(cfg["N"]), want_psi)
+            outs.append(o)
         P[i] = physics(cfg)
         TT[i] = ttable(cfg, keep)
         IN[i] = init(cfg, keep)
         B[i] = batch(cfg, precision, QT_FORM_FUSED)
         RS[i] = r
     check(lib().qt_run_many(ctx.h, k, P, TT, IN, B, RS, _stream_handle(stream)), "qt_run_many")
-    return outs
+    return flat_out if flat else outs
 
 
 # -------------------------------------------------------------------- jobs --

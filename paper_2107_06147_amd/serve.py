@@ -27,8 +27,27 @@ def replay(ctx, requests, precision=qt.QT_FP32_BULK, segment_steps=500, rate_sca
                     hbm_budget_bytes=hbm_budget_bytes)
     ids = []
     t_submit = {}
-    lat = {}
+    t_done = {}
     lock = threading.Lock()
+    submitted = threading.Event()
+
+    def watch():
+        # completion times, taken while requests are still being submitted
+        while True:
+            with lock:
+                open_ids = [r for r in ids if r not in t_done]
+                finished_submitting = submitted.is_set()
+            if finished_submitting and not open_ids:
+                return
+            for r in open_ids:
+                if srv.poll(r):
+                    now = time.perf_counter()
+                    with lock:
+                        t_done[r] = now
+            time.sleep(0.001)
+
+    watcher = threading.Thread(target=watch, daemon=True)
+    watcher.start()
     start = time.perf_counter()
     offered = 0
     for (t_arr, cfg) in requests:
@@ -37,15 +56,16 @@ def replay(ctx, requests, precision=qt.QT_FP32_BULK, segment_steps=500, rate_sca
         delay = start + t_arr * rate_scale - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
+        t0 = time.perf_counter()
         rid = srv.submit(cfg)
         with lock:
-            t_submit[rid] = time.perf_counter()
-        ids.append(rid)
+            t_submit[rid] = t0
+            ids.append(rid)
         offered += int(cfg["n_traj"])
-    results = {}
-    for rid in ids:
-        results[rid] = srv.wait(rid)
-        lat[rid] = time.perf_counter() - t_submit[rid]
+    submitted.set()
+    watcher.join()
+    results = {rid: srv.wait(rid) for rid in ids}
+    lat = {rid: t_done[rid] - t_submit[rid] for rid in ids}
     wall = time.perf_counter() - start
     stats = srv.stats()
     srv.close()
@@ -62,6 +82,17 @@ def replay(ctx, requests, precision=qt.QT_FP32_BULK, segment_steps=500, rate_sca
         "traj_steps_per_s_wall": stats["traj_steps"] / wall if wall > 0 else None,
         "wall_s": wall,
     }, results
+
+
+def offered_load(duration_s=30.0, rate=20.0):
+    """Trajectory-steps per second that the stream offers at `rate`
+    requests/s (mean over `duration_s` seconds of arrivals).  Every request
+    runs its whole temperature table, (tau_end - tau_start)/dt steps."""
+    reqs = W.c4_requests(duration_s=duration_s, rate=rate)
+    total = 0.0
+    for (_, cfg) in reqs:
+        total += int(cfg["n_traj"]) * (float(cfg["tau"][-1]) - float(cfg["tau_start"])) / float(cfg["dt"])
+    return total / duration_s
 
 
 def bench_stream(ctx, duration_s=6.0, rate_scale=1.0, steps_cap=None, segment_steps=500):

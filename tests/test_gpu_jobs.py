@@ -98,6 +98,28 @@ def test_run_many_uneven_equals_separate_runs(ctx):
         compare(oracle.run(c, want_psi=True), qt.to_numpy(o), F64, label="many N=%d" % c["N"])
 
 
+def test_run_many_flat_equals_per_batch(ctx):
+    """flat=True puts every batch's results one after the other in one set of
+    tensors, equal to the per-batch results; batches that share N and L
+    share their tables on the device."""
+    import torch
+    cfgs = W.c3_uneven(n_traj=12)
+    for i, c in enumerate(cfgs):
+        c["max_steps"] = 25 + 7 * i
+        c["n_traj"] = 1 + (i % 3)
+    per = qt.run_many(ctx, cfgs, precision=F32)
+    flat = qt.run_many(ctx, cfgs, precision=F32, flat=True)
+    torch.cuda.synchronize()
+    row = 0
+    for c, o in zip(cfgs, per):
+        n = int(c["n_traj"])
+        a = qt.to_numpy(o)
+        b = {k: v[row:row + n] for k, v in qt.to_numpy(flat).items()}
+        row += n
+        _same(a, b)
+    assert row == len(flat["norm"])
+
+
 # ------------------------------------------------------------------ server --
 
 def _requests():

@@ -144,3 +144,30 @@ def test_determinism(ctx):
     b = gpu_run(ctx, cfg, F32)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+# ------------------------------------------------ unitarity with kappa = 0
+
+# FP64: every step multiplies by unit-modulus factors (static phase, thermal
+# phase, kinetic factor, FFT twiddles) whose moduli are 1 only to an ulp, and
+# the same factors recur step after step, so their rounding adds up: a few
+# 1e-16 per factor and step, ~1e-12 after 1000 steps (measured 2.9e-12; the
+# oracle's naive transform, with fewer factors, 3e-13).  FP32-bulk
+# renormalises the unitary block every step.
+@pytest.mark.parametrize("prec,tol", [(F64, 1e-11), (F32, 1e-5)])
+def test_unitary_evolution_keeps_the_norm(ctx, prec, tol):
+    """Without the imaginary potential every sub-step is unitary: after 1000
+    steps (thermal shift on, Bjorken cooling, l = 1 octet included) the norm
+    stays 1 to rounding; the oracle agrees."""
+    tau, T = W.bjorken_table(0.45, 0.6, 0.25, 500)
+    cfg = W.base(N=1024, L=20.0, dt=0.001, kappa_hat=0.0, gamma_hat=-2.0, do_jumps=0,
+                 tau=tau, T=T, tau_start=float(tau[0]), T_final=0.25, max_steps=1000,
+                 init_kind=W.INIT_GAUSSIAN, init_l=1, init_color=W.OCTET, init_width=1.0,
+                 n_traj=3, seed=7)
+    out = gpu_run(ctx, cfg, prec)
+    drift = float(np.max(np.abs(out["norm"] - 1.0)))
+    print("norm drift", prec, drift)
+    assert np.all(out["steps_done"] == 1000)
+    assert drift <= tol
+    ref = oracle.run(cfg, n_traj=1)
+    assert abs(ref["norm"][0] - 1.0) <= 1e-12
