@@ -318,23 +318,27 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
         return QT_OK;
     }
     const bool f32 = prec == QT_FP32_BULK;
-    std::vector<double> tw(2 * (size_t)N), sn(N);
+    // FFT twiddles exp(-2 pi i m/N); DST pre-processing weights
+    // ((s + 1/2)/2, (s - 1/2)/2) with s = sin(pi m/N)
+    std::vector<double> tw(2 * (size_t)N), sn(2 * (size_t)N);
     for (int m = 0; m < N; ++m) {
         tw[2 * m] = std::cos(2.0 * kPi * m / N);
         tw[2 * m + 1] = -std::sin(2.0 * kPi * m / N);
-        sn[m] = std::sin(kPi * m / N);
+        const double s = std::sin(kPi * m / N);
+        sn[2 * m] = 0.5 * (s + 0.5);
+        sn[2 * m + 1] = 0.5 * (s - 0.5);
     }
     qt_context::Tables t;
     const size_t eb = f32 ? 4 : 8;
     QT_HIP(hipMalloc(&t.tw, 2 * N * eb));
-    QT_HIP(hipMalloc(&t.sines, N * eb));
+    QT_HIP(hipMalloc(&t.prew, 2 * N * eb));
     if (f32) {
         std::vector<float> a(tw.begin(), tw.end()), b(sn.begin(), sn.end());
         QT_HIP(hipMemcpy(t.tw, a.data(), a.size() * 4, hipMemcpyHostToDevice));
-        QT_HIP(hipMemcpy(t.sines, b.data(), b.size() * 4, hipMemcpyHostToDevice));
+        QT_HIP(hipMemcpy(t.prew, b.data(), b.size() * 4, hipMemcpyHostToDevice));
     } else {
         QT_HIP(hipMemcpy(t.tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
-        QT_HIP(hipMemcpy(t.sines, sn.data(), sn.size() * 8, hipMemcpyHostToDevice));
+        QT_HIP(hipMemcpy(t.prew, sn.data(), sn.size() * 8, hipMemcpyHostToDevice));
     }
     ctx->tables[key] = t;
     *out = t;
@@ -609,7 +613,7 @@ qt_status qt_context_destroy(qt_context* ctx)
     hipDeviceSynchronize();
     for (auto& kv : ctx->tables) {
         hipFree(kv.second.tw);
-        hipFree(kv.second.sines);
+        hipFree(kv.second.prew);
     }
     for (auto& kv : ctx->phase) hipFree(kv.second);
     for (hipStream_t s : ctx->aux) hipStreamDestroy(s);
@@ -697,7 +701,7 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
         a.n_items = (int32_t)count[c];
         a.queue = reinterpret_cast<int32_t*>(base) + c;
         a.tw = t.tw;
-        a.sines = t.sines;
+        a.prew = t.prew;
         a.seg_steps = 0;
         const int grid = (int)std::min<int64_t>((int64_t)count[c], (int64_t)ctx->n_cu * v.slots_per_cu);
         QT_HIP(launch_queue_reset(a.queue, s));
@@ -784,7 +788,7 @@ qt_status run_plain(qt_context* ctx, const HostBatch& hb, const qt_results& out,
     a.n_traj = nt;
     a.N = N;
     a.tw = t.tw;
-    a.sines = t.sines;
+    a.prew = t.prew;
     QT_HIP(hipEventRecord(ctx->ev0, s));
     int64_t launches = 0;
     if (nt > 0) {

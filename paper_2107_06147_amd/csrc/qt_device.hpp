@@ -47,8 +47,6 @@ template <class R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b)
     return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
 }
 template <class R> __device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return mk(a.re * s, a.im * s); }
-// multiply by i/2
-template <class R> __device__ __forceinline__ cx<R> mul_ihalf(cx<R> a) { return mk(R(-0.5) * a.im, R(0.5) * a.re); }
 template <class R> __device__ __forceinline__ double abs2d(cx<R> a)
 {
     double x = (double)a.re, y = (double)a.im;
@@ -457,33 +455,36 @@ __device__ __forceinline__ cx<R> block_exclusive_scan(cx<R> x, cx<R>* wsum)
     return exc;
 }
 
-// sin(pi m/N) at the points of the mirror layout: sn[r] for a[r], sn[R1 + r]
-// for b[r] (the same for both transforms of a step).
+// Pre-processing weights of the points a[r] of the mirror layout (see
+// dst1): pw[r] = (p, q) at m = ja + r T.  The same for both transforms of a
+// step.
 template <class R, int N, int W>
-__device__ __forceinline__ void load_sines(R* sn, const R* sines, const Lanes<N, W>& ln)
+__device__ __forceinline__ void load_prew(cx<R>* pw, const cx<R>* prew, const Lanes<N, W>& ln)
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
-    sines = opaque(sines);
-    sfor<0, R1>([&](auto Rr) QT_INL {
-        sn[Rr] = ldg(sines, ln.ja + Rr * T);
-        sn[R1 + Rr] = ldg(sines, ln.jb + Rr * T);
-    });
+    prew = opaque(prew);
+    sfor<0, R1>([&](auto Rr) QT_INL { pw[Rr] = ldg(prew, ln.ja + Rr * T); });
 }
 
 // ------------------------------------------------------------- DST-I ------
 //
 // F_k = sum_{m=1}^{N-1} x_m sin(pi m k / N) on complex data with one complex
 // FFT of length N (the sine transform is real, so it acts on re and im
-// alike):
-//   y_m = sin(pi m/N) (x_m + x_{N-m}) + (x_m - x_{N-m})/2,   Y = FFT_N(y),
+// alike).  With s_m = sin(pi m/N):
+//   y_m = s_m (x_m + x_{N-m}) + (x_m - x_{N-m})/2,   Y = FFT_N(y),
 //   F_{2k}   = (i/2) (Y_k - Y_{N-k}),
 //   D_k      = (Y_k + Y_{N-k})/2 = F_{2k+1} - F_{2k-1},
 //   F_{2k+1} = sum_{q=0}^{k} D_q - Y_0/2.
-// On entry a/b hold x in the mirror layout and sn the matching sin(pi m/N)
-// (sn[r] for a[r], sn[R1 + r] for b[r]; see load_sines).  On exit a/b hold
-// F (times the kinetic factor of each output if KIN) in the same layout.
+// The pre-processing is done on the pair (m, N-m) at once and computes y/2:
+//   y_m/2 = p_m x_m + q_m x_{N-m},  y_{N-m}/2 = p_m x_{N-m} + q_m x_m,
+// p = (s + 1/2)/2, q = (s - 1/2)/2 (s_{N-m} = s_m); the halving cancels the
+// factors 1/2 of the post-processing.
+// On entry a/b hold x in the mirror layout and pw the weights (load_prew);
+// prew is the weight table (lane 0 reads its second column from it).  On
+// exit a/b hold F (times the kinetic factor of each output if KIN) in the
+// same layout.
 template <class R, int N, int W, bool KIN>
-__device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* sn,
+__device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const cx<R>* prew,
                                      const Lanes<N, W>& ln_in, cx<R>* buf, cx<R>* wsum,
                                      const cx<R>* __restrict__ tw,
                                      const Kin<R>* __restrict__ kin)
@@ -494,39 +495,78 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* sn,
     const Lanes<N, W> ln(opaque_lane(ln_in.t));
     const bool lane0 = ln.t == 0;
     cx<R> v[PL::P];
-    const R half = R(0.5);
-    // pre-processing
+    auto mix = [](cx<R> x, cx<R> y, cx<R> w) QT_INL {
+        return mk(w.re * x.re + w.im * y.re, w.re * x.im + w.im * y.im);
+    };
+    // pre-processing.  Every lane but 0: the mirror of a[r] (m = t + r T) is
+    // b[R1-1-r] (N - m = T - t + (R1-1-r) T).
     sfor<0, R1>([&](auto Rr) QT_INL {
         constexpr int r = Rr;
-        cx<R> xa = a[r];
-        cx<R> ma = pick(lane0, a[(R1 - r) % R1], b[R1 - 1 - r]);
-        v[r] = scale(xa + ma, sn[r]) + scale(xa - ma, half);
-        cx<R> xb = b[r];
-        cx<R> mb = pick(lane0, b[R1 - 1 - r], a[R1 - 1 - r]);
-        v[R1 + r] = scale(xb + mb, sn[R1 + r]) + scale(xb - mb, half);
+        const cx<R> x = a[r], y = b[R1 - 1 - r];
+        v[r] = mix(x, y, pw[r]);
+        v[2 * R1 - 1 - r] = mix(y, x, pw[r]);
     });
+    if (lane0) {
+        // lane 0 holds m = r T (mirror (R1 - r) T, itself for r = 0 and
+        // R1/2) and m = W + r T (mirror W + (R1-1-r) T): redone here, by
+        // the first wave only
+        sfor<0, R1 / 2 + 1>([&](auto Rr) QT_INL {
+            constexpr int r = Rr;
+            constexpr int rm = (R1 - r) % R1;
+            const cx<R> x = a[r], y = a[rm];
+            v[r] = mix(x, y, pw[r]);
+            if constexpr (rm != r) v[rm] = mix(y, x, pw[r]);
+        });
+        const cx<R>* tab = opaque(prew);
+        sfor<0, R1 / 2>([&](auto Rr) QT_INL {
+            constexpr int r = Rr;
+            const cx<R> w = ldg(tab, W + r * T);
+            const cx<R> x = b[r], y = b[R1 - 1 - r];
+            v[R1 + r] = mix(x, y, w);
+            v[2 * R1 - 1 - r] = mix(y, x, w);
+        });
+    }
     {
         PassTwiddles<R, N, W, 0> none;
         fft_passes<R, N, W, 0>(v, ln, buf, tw, none);
     }
-    // post-processing: pairs (k, N-k), even outputs and differences D_k
+    // post-processing: pairs (k, N-k), even outputs F_{2k} and differences
+    // D_k for k < N/2 (Y here is half the FFT of y)
+    auto mul_i = [](cx<R> z) QT_INL { return mk(-z.im, z.re); };
     sfor<0, R1 / 2>([&](auto Rr) QT_INL {
         constexpr int r = Rr;
-        {
-            cx<R> y = v[r];
-            cx<R> yp = pick(lane0, v[(R1 - r) % R1], v[R1 + R1 - 1 - r]);
+        {   // k = ja + r T, N - k = jb + (R1-1-r) T
+            const cx<R> y = v[r], yp = v[2 * R1 - 1 - r];
             cx<R>* dst = buf + pad(2 * ln.ja);
-            dst[padc<2 * r * T>()] = mul_ihalf(y - yp);
-            dst[padc<2 * r * T>() + 1] = scale(y + yp, half);
+            dst[padc<2 * r * T>()] = mul_i(y - yp);
+            dst[padc<2 * r * T>() + 1] = y + yp;
         }
-        {
-            cx<R> y = v[R1 + r];
-            cx<R> yp = pick(lane0, v[R1 + R1 - 1 - r], v[R1 - 1 - r]);
+        {   // k = jb + r T, N - k = ja + (R1-1-r) T
+            const cx<R> y = v[R1 + r], yp = v[R1 - 1 - r];
             cx<R>* dst = buf + pad(2 * ln.jb);
-            dst[padc<2 * r * T>()] = mul_ihalf(y - yp);
-            dst[padc<2 * r * T>() + 1] = scale(y + yp, half);
+            dst[padc<2 * r * T>()] = mul_i(y - yp);
+            dst[padc<2 * r * T>() + 1] = y + yp;
         }
     });
+    if (lane0) {
+        // lane 0: N - r T = (R1 - r) T and N - (W + r T) = W + (R1-1-r) T;
+        // rewrites its entries
+        sfor<0, R1 / 2>([&](auto Rr) QT_INL {
+            constexpr int r = Rr;
+            {
+                const cx<R> y = v[r], yp = v[(R1 - r) % R1];
+                cx<R>* dst = buf + pad(2 * ln.ja);
+                dst[padc<2 * r * T>()] = mul_i(y - yp);
+                dst[padc<2 * r * T>() + 1] = y + yp;
+            }
+            {
+                const cx<R> y = v[R1 + r], yp = v[2 * R1 - 1 - r];
+                cx<R>* dst = buf + pad(2 * ln.jb);
+                dst[padc<2 * r * T>()] = mul_i(y - yp);
+                dst[padc<2 * r * T>() + 1] = y + yp;
+            }
+        });
+    }
     // kinetic factors of the outputs this lane ends up holding (mirror
     // layout), loaded here so that the exchanges below hide their latency
     Kin<R> kk[KIN ? PL::P : 1];
@@ -548,7 +588,7 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const R* sn,
         run = run + chunk[padc<2 * I + 1>()];
         pre[I] = run;
     });
-    const cx<R> off = block_exclusive_scan<W>(run, wsum) - scale(d0, half);
+    const cx<R> off = block_exclusive_scan<W>(run, wsum) - scale(d0, R(0.5));
     sfor<0, CH>([&](auto I) QT_INL { chunk[padc<2 * I + 1>()] = pre[I] + off; });
     __syncthreads();
     // F * kin (FP32: hi and lo parts of the double-float factor)

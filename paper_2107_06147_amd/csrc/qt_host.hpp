@@ -15,7 +15,7 @@ struct qt_context {
     int device = 0;
     int n_cu = 0;
     std::mutex mu;
-    struct Tables { void* tw = nullptr; void* sines = nullptr; };
+    struct Tables { void* tw = nullptr; void* prew = nullptr; };
     std::map<std::pair<int, int>, Tables> tables;          // (precision, N)
     struct Variant { int W = 0; int slots_per_cu = 0; bool tuned = false; };
     std::map<std::pair<int, int>, Variant> plans;          // (precision, N)

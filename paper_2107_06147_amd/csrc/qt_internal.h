@@ -45,7 +45,7 @@ struct FusedArgs {
     int32_t          n_items;
     int32_t*         queue;
     const void*      tw;      // N complex: exp(-2 pi i m / N)
-    const void*      sines;   // N reals: sin(pi m / N)
+    const void*      prew;   // N complex: ((s+1/2)/2, (s-1/2)/2), s = sin(pi m / N)
     int64_t          seg_steps;   // <= 0: run to the end
 };
 
@@ -70,7 +70,7 @@ struct PlainArgs {
     int64_t    n_traj;
     int32_t    N;
     const void* tw;
-    const void* sines;
+    const void* prew;
 };
 hipError_t plain_init(const PlainArgs& a, hipStream_t s);
 hipError_t plain_space(const PlainArgs& a, int64_t n, hipStream_t s);

@@ -159,7 +159,7 @@ qt_status qt_job_create(qt_context* ctx, const qt_physics* phys, const qt_ttable
     j->args.n_items = (int32_t)j->n_traj;
     j->args.queue = j->queue;
     j->args.tw = t.tw;
-    j->args.sines = t.sines;
+    j->args.prew = t.prew;
     j->args.seg_steps = segment_steps;
     j->grid = (int)std::min<int64_t>(std::max<int64_t>(j->n_traj, 1), (int64_t)ctx->n_cu * v.slots_per_cu);
     *out = j;

@@ -369,7 +369,7 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
 
     const Lanes<N, W> ln(threadIdx.x);
     const cx<R>* tw = static_cast<const cx<R>*>(A.tw);
-    const R* sines = static_cast<const R*>(A.sines);
+    const cx<R>* prew = static_cast<const cx<R>*>(A.prew);
 
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(A.queue, 1);
@@ -439,8 +439,8 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
             const bool fast = !kRenorm || (fabs(-0.5 * g.dt * cc * g.kappa_hat * T3) * xmax <= 0.5 &&
                                            fabs(-0.5 * g.dt * cc * g.gamma_hat * T3) * xmax <= 0.78);
 
-            R sn[Plan<N, W>::P];
-            load_sines<R, N, W>(sn, sines, ls);
+            cx<R> pw[Plan<N, W>::R1];
+            load_prew<R, N, W>(pw, prew, ls);
             R dm[Plan<N, W>::P];
             double n_in = 0.0;
             with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
@@ -448,8 +448,8 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
                 n_in = first_half<R, N, W, G, F, kCache, kRenorm>(a, b, h, ls, fac, dm);
             });
             const cx<R>* tw_n = opaque(tw);
-            dst1<R, N, W, true>(a, b, sn, ls, buf, wsum, tw_n, kin);
-            dst1<R, N, W, false>(a, b, sn, ls, buf, wsum, opaque(tw_n), nullptr);
+            dst1<R, N, W, true>(a, b, pw, prew, ls, buf, wsum, tw_n, kin);
+            dst1<R, N, W, false>(a, b, pw, prew, ls, buf, wsum, opaque(tw_n), nullptr);
             // x: sum |D u|^2 after the first half-step (the norm the unitary
             // block receives), sum |C u|^2 (what it returns), sum |D C u|^2
             double x[3] = {n_in, 0.0, 0.0};
@@ -670,7 +670,7 @@ __global__ void plain_kinetic_kernel(const GroupDesc* gp, double* psi, const Tra
 
 template <int N, int W>
 __global__ __launch_bounds__(W) void plain_dst_kernel(double* psi, const TrajState* st,
-                                                      const void* twv, const void* sinv)
+                                                      const void* twv, const void* prewv)
 {
     using PL = Plan<N, W>;
     constexpr int R1 = PL::R1, T = PL::T;
@@ -679,16 +679,16 @@ __global__ __launch_bounds__(W) void plain_dst_kernel(double* psi, const TrajSta
     const int64_t tr = blockIdx.x;
     if (st[tr].done) return;
     const Lanes<N, W> ln(threadIdx.x);
-    const double* sines = static_cast<const double*>(sinv);
+    const cx<double>* prew = static_cast<const cx<double>*>(prewv);
     cx<double> a[R1], b[R1];
     cx<double>* u = reinterpret_cast<cx<double>*>(psi) + (size_t)tr * N;
     sfor<0, R1>([&](auto Rr) QT_INL {
         a[Rr] = u[ln.ja + Rr * T];
         b[Rr] = u[ln.jb + Rr * T];
     });
-    double sn[Plan<N, W>::P];
-    load_sines<double, N, W>(sn, sines, ln);
-    dst1<double, N, W, false>(a, b, sn, ln, buf, wsum, static_cast<const cx<double>*>(twv), nullptr);
+    cx<double> pw[Plan<N, W>::R1];
+    load_prew<double, N, W>(pw, prew, ln);
+    dst1<double, N, W, false>(a, b, pw, prew, ln, buf, wsum, static_cast<const cx<double>*>(twv), nullptr);
     sfor<0, R1>([&](auto Rr) QT_INL {
         u[ln.ja + Rr * T] = a[Rr];
         u[ln.jb + Rr * T] = b[Rr];
@@ -869,7 +869,7 @@ template <int N, int W>
 static hipError_t plain_dst_n(const PlainArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL((plain_dst_kernel<N, W>), dim3((unsigned)a.n_traj), dim3(W), 0, s, a.psi,
-                       a.st, a.tw, a.sines);
+                       a.st, a.tw, a.prew);
     return hipGetLastError();
 }
 

@@ -209,7 +209,7 @@ qt_status run_round(qt_server* s, int64_t* advanced)
         a.n_items = (int32_t)count[c];
         a.queue = queues + c;
         a.tw = t.tw;
-        a.sines = t.sines;
+        a.prew = t.prew;
         a.seg_steps = s->cfg.segment_steps;
         const int grid = (int)std::min<int64_t>((int64_t)count[c], (int64_t)s->ctx->n_cu * v.slots_per_cu);
         QT_HIP(launch_queue_reset(a.queue, s->stream));
