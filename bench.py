@@ -164,8 +164,8 @@ def main():
         profile_mode(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (trajectories are independent; "
-              "a multi-GPU run would shard trajectory ids, see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: --gpus must be 1 (trajectories are independent; "
+              "several GPUs would each take a range of trajectory ids)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -1,10 +1,13 @@
 """Helpers of the GPU-vs-oracle parity tests.
 
-Tolerances (derived in DESIGN.md "Parity bar"):
+Tolerances:
   FP64 (fused and plain): wave function ||u_gpu - u_ora|| / ||u_ora|| <= 1e-10,
-      norm and overlaps/survival probabilities within 1e-10 absolute.
-  FP32-bulk: the measured accumulation of single-precision rounding over the
-      run, see FP32_TOL; the norm and the threshold are FP64 on both sides.
+      norm and overlaps/survival probabilities within 1e-10 absolute (the
+      two sides differ only in summation order and transform algorithm:
+      ~1e-15 per step, measured ~7e-13 after 1000 steps).
+  FP32-bulk: single-precision rounding of ~6e-8 per operation, a few dozen
+      operations per point and step, accumulated over up to 1e3 steps, see
+      FP32_TOL; the norm and the threshold are FP64 on both sides.
 A jump decision is near the threshold when the oracle's smallest
 |norm - r| over the run is <= delta (1e-9 FP64, FP32_DELTA FP32); such
 trajectories are counted and their wave functions are not compared (the two
