@@ -23,7 +23,7 @@ _lib = None
 
 SINGLET, OCTET = 0, 1
 INIT_COULOMB, INIT_GAUSSIAN, INIT_ARRAY = 0, 1, 2
-STATUS_OK, STATUS_RMAX, STATUS_MAXJUMPS = 0, 1, 2
+STATUS_OK, STATUS_RMAX, STATUS_MAXJUMPS, STATUS_NOJUMP = 0, 1, 2, 4
 FLAG_KINETIC_OFF = 1
 BASIS = ("1S", "2S", "1P", "3S", "2P", "1D")
 
@@ -51,7 +51,8 @@ class _Physics(C.Structure):
 class _TTable(C.Structure):
     _fields_ = [("tau", C.POINTER(C.c_double)), ("T", C.POINTER(C.c_double)),
                 ("n", C.c_int32), ("tau_start", C.c_double),
-                ("T_final", C.c_double), ("max_steps", C.c_int64)]
+                ("T_final", C.c_double), ("max_steps", C.c_int64),
+                ("vacuum_steps", C.c_int64)]
 
 
 class _Init(C.Structure):
@@ -62,7 +63,7 @@ class _Init(C.Structure):
 
 class _Batch(C.Structure):
     _fields_ = [("n_traj", C.c_int64), ("seed", C.c_uint64), ("traj_id0", C.c_uint64),
-                ("traj_id_stride", C.c_uint64)]
+                ("traj_id_stride", C.c_uint64), ("no_jump_shortcut", C.c_int32)]
 
 
 _D = C.POINTER(C.c_double)
@@ -126,7 +127,8 @@ def _ttable(cfg, keep):
     T = np.ascontiguousarray(cfg["T"], dtype=np.float64)
     keep += [tau, T]
     return _TTable(_dptr(tau), _dptr(T), len(tau), float(cfg["tau_start"]),
-                   float(cfg.get("T_final", 0.0)), int(cfg.get("max_steps", 2**62)))
+                   float(cfg.get("T_final", 0.0)), int(cfg.get("max_steps", 2**62)),
+                   int(cfg.get("vacuum_steps", 0)))
 
 
 def _init(cfg, keep):
@@ -158,7 +160,8 @@ def run(cfg, n_traj=None, traj_id0=None, want_psi=False, want_trace=False,
     p = _physics(cfg)
     tt = _ttable(cfg, keep)
     ini = _init(cfg, keep)
-    b = _Batch(n, int(cfg.get("seed", 1)), t0, int(cfg.get("traj_id_stride", 1)))
+    b = _Batch(n, int(cfg.get("seed", 1)), t0, int(cfg.get("traj_id_stride", 1)),
+               int(cfg.get("no_jump_shortcut", 0)))
     n_steps = int(lib().qto_num_steps(C.byref(p), C.byref(tt)))
     N = int(cfg["N"])
     out = {

@@ -381,9 +381,42 @@ typedef struct {
     const double* tab; const double* mom_re; const double* mom_im;
     const double* basis; const double* init_re; const double* init_im;
     double init_overlap[6];
+    /* the zeroth trajectory (no_jump_shortcut): its smallest norm over the
+       run, and its results in `zeroth` (one entry, with its norm trace) */
+    int have_zeroth;
+    double r_min;
+    const qto_results* zeroth;
 } shared_setup;
 
-static void run_one(const shared_setup* s, int64_t i, workspace* w)
+/* Copies entry 0 of the zeroth trajectory's results to entry i: a trajectory
+ * whose first threshold r lies below every norm of the no-jump evolution
+ * never jumps, so its evolution is that evolution (Sec. "Summary of QTraj
+ * execution", step 4: r_0 < rMin = p_NoJumps).  Only first_r, the gap and
+ * the status are its own. */
+static void take_zeroth(const shared_setup* s, int64_t i, double r)
+{
+    const qto_results* z = s->zeroth;
+    qto_results* out = s->out;
+    int32_t N = s->p->N;
+    if (out->norm) out->norm[i] = z->norm[0];
+    if (out->first_r) out->first_r[i] = r;
+    if (out->overlap) for (int bb = 0; bb < 6; ++bb) out->overlap[6 * i + bb] = z->overlap[bb];
+    if (out->survival) for (int bb = 0; bb < 6; ++bb) out->survival[6 * i + bb] = z->survival[bb];
+    if (out->mean_r) out->mean_r[i] = z->mean_r[0];
+    if (out->l) out->l[i] = z->l[0];
+    if (out->color) out->color[i] = z->color[0];
+    if (out->n_jumps) out->n_jumps[i] = 0;
+    if (out->status) out->status[i] = QTO_STATUS_NOJUMP;
+    if (out->steps_done) out->steps_done[i] = z->steps_done[0];
+    if (out->min_gap) out->min_gap[i] = s->r_min - r;
+    if (out->psi) memcpy(out->psi + (size_t)i * 2 * N, z->psi, sizeof(double) * 2 * N);
+    if (out->norm_trace)
+        memcpy(out->norm_trace + i * s->n_steps, z->norm_trace, sizeof(double) * s->n_steps);
+}
+
+/* zeroth != 0: the zeroth trajectory, whose threshold is 0 so that it never
+ * jumps; its gap min |norm - 0| is then its smallest norm. */
+static void run_one(const shared_setup* s, int64_t i, workspace* w, int zeroth)
 {
     const qto_physics* p = s->p;
     int32_t N = p->N;
@@ -402,10 +435,14 @@ static void run_one(const shared_setup* s, int64_t i, workspace* w)
     /* the first threshold r_0 */
     uint64_t wd[4];
     event_block(s->b->seed, traj_id, 0, wd);
-    double r = qto_uniform(wd[2]);
+    double r = zeroth ? 0.0 : qto_uniform(wd[2]);
     double first_r = r;
     double norm = norm_of(N, dr, w->re, w->im);
 
+    if (!zeroth && s->have_zeroth && r < s->r_min) {
+        take_zeroth(s, i, r);
+        return;
+    }
     if (p->do_jumps && r > p->r_max) {
         status = QTO_STATUS_RMAX;
     } else {
@@ -474,7 +511,7 @@ static int validate(const qto_physics* p, const qto_ttable* tt, const qto_init* 
     if (p->kappa_hat < 0 || p->gamma_hat > 0) return -4;
     if (p->deriv_type != 0 && p->deriv_type != 1) return -5;
     if (!(p->r_max > 0) || p->r_max > 1) return -6;
-    if (!tt->tau || !tt->T || tt->n < 2 || tt->max_steps < 0) return -7;
+    if (!tt->tau || !tt->T || tt->n < 2 || tt->max_steps < 0 || tt->vacuum_steps < 0) return -7;
     for (int32_t k = 0; k + 1 < tt->n; ++k) if (!(tt->tau[k + 1] > tt->tau[k])) return -7;
     if (ini->l < 0 || (ini->color != QTO_SINGLET && ini->color != QTO_OCTET)) return -8;
     if (ini->kind == QTO_INIT_ARRAY && !ini->u_re) return -8;
@@ -517,9 +554,49 @@ int qto_run(const qto_physics* p, const qto_ttable* tt, const qto_init* ini,
         free(tab); free(mom_re); free(mom_im); free(basis); free(init_re); free(init_im);
         return -10;
     }
+    /* survival ratios refer to the prepared state, before any vacuum phase */
     singlet_overlaps(N, dr, basis, ini->l, ini->color, init_re, init_im, s.init_overlap);
     s.tab = tab; s.mom_re = mom_re; s.mom_im = mom_im; s.basis = basis;
     s.init_re = init_re; s.init_im = init_im;
+
+    double* buf0 = (double*)calloc((size_t)6 * N, sizeof(double));
+    workspace w0;
+    w0.re = buf0; w0.im = buf0 + N; w0.tre = buf0 + 2 * N; w0.tim = buf0 + 3 * N;
+    w0.kre = buf0 + 4 * N; w0.kim = buf0 + 5 * N;
+    /* in-vacuum evolution (T = 0) of the initial state, once, then stored as
+       the state every trajectory starts from */
+    if (tt->vacuum_steps > 0) {
+        memcpy(w0.re, init_re, sizeof(double) * N);
+        memcpy(w0.im, init_im, sizeof(double) * N);
+        for (int64_t n = 0; n < tt->vacuum_steps; ++n) {
+            load_space_kernel(p, ini->l, ini->color, 0.0, &w0);
+            make_step(N, tab, &w0, mom_re, mom_im);
+        }
+        memcpy(init_re, w0.re, sizeof(double) * N);
+        memcpy(init_im, w0.im, sizeof(double) * N);
+    }
+    /* the zeroth trajectory (jumps impossible), its results kept for the
+       trajectories that cannot jump */
+    qto_results zres;
+    memset(&zres, 0, sizeof zres);
+    double* zbuf = NULL;
+    if (b->no_jump_shortcut && p->do_jumps) {
+        int64_t ns = s.n_steps;
+        zbuf = (double*)calloc((size_t)(17 + 2 * N + ns), sizeof(double));
+        int32_t* zint = (int32_t*)calloc(4, sizeof(int32_t));
+        int64_t* zsteps = (int64_t*)calloc(1, sizeof(int64_t));
+        zres.norm = zbuf; zres.first_r = zbuf + 1; zres.overlap = zbuf + 2;
+        zres.survival = zbuf + 8; zres.mean_r = zbuf + 14; zres.min_gap = zbuf + 15;
+        zres.psi = zbuf + 17; zres.norm_trace = ns > 0 ? zbuf + 17 + 2 * N : NULL;
+        zres.l = zint; zres.color = zint + 1; zres.n_jumps = zint + 2; zres.status = zint + 3;
+        zres.steps_done = zsteps;
+        shared_setup sz = s;
+        sz.out = &zres;
+        run_one(&sz, 0, &w0, 1);
+        s.have_zeroth = 1;
+        s.r_min = zres.min_gap[0];
+        s.zeroth = &zres;
+    }
 
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -533,9 +610,13 @@ int qto_run(const qto_physics* p, const qto_ttable* tt, const qto_init* ini,
         w.re = buf; w.im = buf + N; w.tre = buf + 2 * N; w.tim = buf + 3 * N;
         w.kre = buf + 4 * N; w.kim = buf + 5 * N;
 #pragma omp for schedule(dynamic, 1)
-        for (int64_t i = 0; i < b->n_traj; ++i) run_one(&s, i, &w);
+        for (int64_t i = 0; i < b->n_traj; ++i) run_one(&s, i, &w, 0);
         free(buf);
     }
+    if (zbuf) {
+        free(zbuf); free(zres.l); free(zres.steps_done);
+    }
+    free(buf0);
     free(tab); free(mom_re); free(mom_im); free(basis); free(init_re); free(init_im);
     return 0;
 }

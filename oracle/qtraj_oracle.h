@@ -26,7 +26,8 @@ extern "C" {
 
 enum { QTO_SINGLET = 0, QTO_OCTET = 1 };
 enum { QTO_INIT_COULOMB = 0, QTO_INIT_GAUSSIAN = 1, QTO_INIT_ARRAY = 2 };
-enum { QTO_STATUS_OK = 0, QTO_STATUS_RMAX = 1, QTO_STATUS_MAXJUMPS = 2 };
+enum { QTO_STATUS_OK = 0, QTO_STATUS_RMAX = 1, QTO_STATUS_MAXJUMPS = 2,
+       QTO_STATUS_NOJUMP = 4 };   /* 4: results taken from the no-jump trajectory */
 enum { QTO_FLAG_KINETIC_OFF = 1 };   /* test flag: kinetic factor := 1 */
 
 typedef struct {
@@ -51,6 +52,10 @@ typedef struct {
     double  tau_start;    /* t_0 of step 0                                    */
     double  T_final;      /* stop once T(t_n) < T_final                       */
     int64_t max_steps;    /* hard cap on the number of steps                  */
+    int64_t vacuum_steps; /* steps of in-vacuum evolution (T = 0, no jumps) of
+                             the initial state before tau_start, done once for
+                             the batch (Sec. "Summary of QTraj execution",
+                             step 3: evolution from t0 until the medium)     */
 } qto_ttable;
 
 typedef struct {
@@ -68,6 +73,10 @@ typedef struct {
     uint64_t seed;
     uint64_t traj_id0;    /* trajectory i of the batch has id               */
     uint64_t traj_id_stride; /* traj_id0 + i * traj_id_stride (0 means 1)    */
+    int32_t  no_jump_shortcut; /* 1: the zeroth (no-jump) trajectory is run
+                             first; a trajectory whose first threshold lies
+                             below its smallest norm cannot jump and takes its
+                             results (status QTO_STATUS_NOJUMP)              */
 } qto_batch;
 
 /* Every pointer may be NULL (output not wanted), except where noted.        */

@@ -320,3 +320,87 @@ def test_overlap_and_survival_definitions(oracle_lib):
             assert abs(res["overlap"][i, b] - ov) < 1e-13
             sv = ov / ov0[b] if ov0[b] != 0 else ov
             assert abs(res["survival"][i, b] - sv) < 1e-12
+
+
+# --------------------------------------- zeroth trajectory and rMin shortcut
+
+def test_no_jump_shortcut_is_exact(oracle_lib):
+    """A trajectory whose first threshold lies below every norm of the
+    no-jump (zeroth) trajectory cannot jump, so it reproduces that
+    trajectory: with the shortcut its results are taken from it, and they
+    equal the full evolution bit for bit; only the status says so (Sec.
+    "Summary of QTraj execution", step 4: r_0 < rMin = p_NoJumps)."""
+    cfg = W.base(N=256, L=20.0, dt=0.002, kappa_hat=4.0, gamma_hat=-1.0, n_traj=64, seed=3,
+                 init_kind=W.INIT_COULOMB, **W.constant_T(0.35, 600))
+    full = oracle.run(cfg, want_psi=True, want_trace=True)
+    fast = oracle.run(dict(cfg, no_jump_shortcut=1), want_psi=True, want_trace=True)
+    took = fast["status"] == oracle.STATUS_NOJUMP
+    assert 0 < took.sum() < len(took)                       # both kinds present
+    assert np.all(full["n_jumps"][took] == 0) and np.all(full["status"][took] == 0)
+    # the shortcut trajectories are exactly those below the zeroth's smallest norm
+    zeroth_min = np.min(full["norm_trace"][took][0])
+    assert np.all(full["first_r"][took] < zeroth_min)
+    assert np.all((full["first_r"][~took] >= zeroth_min) | (full["status"][~took] != 0))
+    for k in full:
+        if k != "status":
+            assert np.array_equal(full[k], fast[k]), k
+    assert np.array_equal(full["status"][~took], fast["status"][~took])
+
+
+def test_no_jump_shortcut_without_steps(oracle_lib):
+    """Zero steps: nothing can jump, every trajectory takes the zeroth's
+    results (the initial state) with an infinite gap."""
+    cfg = W.base(N=256, L=20.0, n_traj=5, no_jump_shortcut=1, **W.constant_T(0.35, 0))
+    out = oracle.run(cfg)
+    assert np.all(out["status"] == oracle.STATUS_NOJUMP)
+    assert np.all(out["steps_done"] == 0) and np.all(np.isinf(out["min_gap"]))
+    assert np.allclose(out["norm"], 1.0, atol=1e-14)
+
+
+# ---------------------------------------------------- in-vacuum evolution
+
+def test_vacuum_phase_is_a_zero_temperature_evolution(oracle_lib):
+    """vacuum_steps steps at T = 0 (whatever the table says) evolve a
+    discrete vacuum eigenstate by its phase exp(-i E t) only: the width and
+    thermal terms are off and the norm stays 1 (Sec. "Summary of QTraj
+    execution", step 3)."""
+    N, L, dt, steps = 512, 40.0, 0.001, 2000
+    M, alpha = W.MASS_B, 4.0 / 3.0 * W.ALPHA_S
+    E, V = np.linalg.eigh(_discrete_hamiltonian(N, L, M, alpha, 0))
+    dr = L / N
+    u0 = np.zeros(N, complex)
+    u0[1:] = V[:, 0] * np.sign(V[np.argmax(np.abs(V[:, 0])), 0])
+    u0 /= np.sqrt(dr * np.sum(np.abs(u0) ** 2))
+    # a hot medium that would damp the state at once, but no medium steps
+    cfg = W.base(N=N, L=L, dt=dt, kappa_hat=8.0, gamma_hat=-3.0, init_kind=W.INIT_ARRAY,
+                 init_l=0, n_traj=2, vacuum_steps=steps, **W.constant_T(0.5, 0))
+    cfg["u0"] = u0
+    out = oracle.run(cfg, want_psi=True)
+    psi = out["psi"][0]
+    assert abs(out["norm"][0] - 1.0) < 1e-12
+    c = dr * np.vdot(u0, psi)
+    assert abs(abs(c) ** 2 - 1.0) < 1e-6
+    assert abs(np.angle(c * np.exp(1j * E[0] * dt * steps))) < 1e-5 * abs(E[0]) * dt * steps + 1e-6
+    # every trajectory starts from the one stored state
+    assert np.array_equal(out["psi"][1], psi)
+    # survival ratios refer to the prepared state (before the vacuum phase)
+    b1s = oracle.basis_state(N, L, M, W.ALPHA_S, 1, 0)
+    init_ov = abs(dr * np.dot(b1s, u0)) ** 2 / (dr * np.sum(np.abs(u0) ** 2))
+    assert abs(out["survival"][0, 0] - out["overlap"][0, 0] / init_ov) < 1e-9
+
+
+def test_vacuum_phase_then_medium_equals_stored_start(oracle_lib):
+    """A run with a vacuum phase equals a run that starts from the state the
+    vacuum phase produced (up to its renormalisation on input)."""
+    base = dict(N=256, L=20.0, dt=0.002, kappa_hat=4.0, gamma_hat=-1.0, n_traj=8, seed=4,
+                init_kind=W.INIT_GAUSSIAN, init_width=1.2, init_l=1)
+    vac = oracle.run(W.base(vacuum_steps=300, **base, **W.constant_T(0.4, 0)), n_traj=1,
+                     want_psi=True)["psi"][0]
+    both = oracle.run(W.base(vacuum_steps=300, **base, **W.constant_T(0.4, 250)), want_psi=True)
+    cfg = W.base(**dict(base, init_kind=W.INIT_ARRAY), **W.constant_T(0.4, 250))
+    cfg["u0"] = vac
+    split = oracle.run(cfg, want_psi=True)
+    for k in ("n_jumps", "l", "color", "status", "steps_done"):
+        assert np.array_equal(both[k], split[k]), k
+    assert np.allclose(both["norm"], split["norm"], atol=1e-12)
+    assert np.allclose(both["psi"], split["psi"], atol=1e-11)
