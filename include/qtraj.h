@@ -72,8 +72,13 @@ typedef enum { QT_FP64 = 0, QT_FP32_BULK = 1 } qt_precision;
 typedef enum { QT_FORM_FUSED = 0, QT_FORM_PLAIN = 1 } qt_form;
 typedef enum { QT_INIT_COULOMB = 0, QT_INIT_GAUSSIAN = 1, QT_INIT_ARRAY = 2 } qt_init_kind;
 typedef enum { QT_SINGLET = 0, QT_OCTET = 1 } qt_color;
-/* LMAX: l exceeded the tabulated range (l > 255; ends like MAXJUMPS). */
-typedef enum { QT_TRAJ_OK = 0, QT_TRAJ_RMAX = 1, QT_TRAJ_MAXJUMPS = 2, QT_TRAJ_LMAX = 3 } qt_traj_status;
+/* LMAX: l exceeded the tabulated range (l > 255; ends like MAXJUMPS).
+ * NOJUMP: the first threshold lies below every norm of the batch's no-jump
+ * (zeroth) trajectory, so the trajectory cannot jump: its results are that
+ * trajectory's (no_jump_shortcut; paper: Sec. "Summary of QTraj execution",
+ * step 4, r_0 < rMin = p_NoJumps). */
+typedef enum { QT_TRAJ_OK = 0, QT_TRAJ_RMAX = 1, QT_TRAJ_MAXJUMPS = 2, QT_TRAJ_LMAX = 3,
+               QT_TRAJ_NOJUMP = 4 } qt_traj_status;
 enum { QT_FLAG_KINETIC_OFF = 1 };   /* kinetic factor := 1 (test special case) */
 
 /* Physics and grid (paper: table "Code parameters", groups Physics, Jump,
@@ -89,13 +94,20 @@ typedef struct {
 } qt_physics;
 
 /* Temperature table (paper: Temperature parameters).  Host pointers, read
- * during the call.  tau in GeV^-1 strictly increasing, n >= 2. */
+ * during the call.  tau in GeV^-1 strictly increasing, n >= 2.
+ * vacuum_steps >= 0: before tau_start the initial state is evolved that many
+ * steps in vacuum (T = 0, no jumps), once for the batch, and every
+ * trajectory starts from the result (paper: Sec. "Summary of QTraj
+ * execution", step 3, evolution from t0 until the medium turns on; the
+ * count is (t_med - t0)/dt).  Survival ratios still refer to the prepared
+ * initial state. */
 typedef struct {
     const double* tau;
     const double* T;
     int32_t n;
     double  tau_start, T_final;
     int64_t max_steps;
+    int64_t vacuum_steps;
 } qt_ttable;
 
 /* Initial state (paper: Initial condition parameters).  COULOMB: hydrogen-
@@ -111,11 +123,16 @@ typedef struct {
 
 /* Trajectory i of a batch has id traj_id0 + i * traj_id_stride (stride 0 is
  * read as 1); ids select the random streams, so results do not depend on
- * how trajectories are batched.  precision: qt_precision; form: qt_form. */
+ * how trajectories are batched.  precision: qt_precision; form: qt_form.
+ * no_jump_shortcut = 1 (qt_run / qt_run_many, FUSED form, jumps on): the
+ * batch's zeroth trajectory (the same evolution with no jumps) runs first;
+ * a trajectory whose first threshold lies below its smallest norm takes its
+ * results, status QT_TRAJ_NOJUMP, exactly as if it had been evolved. */
 typedef struct {
     int64_t  n_traj;
     uint64_t seed, traj_id0, traj_id_stride;
     int32_t  precision, form;
+    int32_t  no_jump_shortcut;
 } qt_batch;
 
 /* Per-trajectory outputs, DEVICE pointers owned by the caller.  Any pointer

@@ -126,6 +126,11 @@ qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in, 
         return fail(QT_EINVAL, "unknown form %d", b->form);
     if (b->form == QT_FORM_PLAIN && b->precision != QT_FP64)
         return fail(QT_EINVAL, "the plain form is FP64 only");
+    if (tt->vacuum_steps < 0) return fail(QT_EINVAL, "vacuum_steps must be >= 0");
+    if (b->no_jump_shortcut != 0 && b->no_jump_shortcut != 1)
+        return fail(QT_EINVAL, "no_jump_shortcut must be 0 or 1");
+    if (b->no_jump_shortcut && b->form != QT_FORM_FUSED)
+        return fail(QT_EINVAL, "the no-jump shortcut runs in the fused form");
     return QT_OK;
 }
 
@@ -293,6 +298,7 @@ qt_status prepare(const qt_physics* p, const qt_ttable* tt, const qt_init* in, c
     hb->tau_start = tt->tau_start;
     hb->T_final = tt->T_final;
     hb->n_steps = count_steps(*p, *tt);
+    hb->vacuum_steps = tt->vacuum_steps;
     hb->kin = kinetic_table(p);
     hb->basis = basis_table(p);
     if (in->kind == QT_INIT_ARRAY) {
@@ -493,6 +499,8 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         d.out = outs[g];
         d.st_psi = nullptr;
         d.st = nullptr;
+        d.zeroth = h.zeroth;
+        d.r_min = h.r_min;
         dg->host[g] = d;
         std::memcpy(&blob[o[g].tau], h.tau.data(), h.tau.size() * 8);
         std::memcpy(&blob[o[g].T], h.T.data(), h.T.size() * 8);
@@ -815,6 +823,116 @@ qt_status run_plain(qt_context* ctx, const HostBatch& hb, const qt_results& out,
     return QT_OK;
 }
 
+qt_status run_vacuum_phases(qt_context* ctx, const std::vector<HostBatch*>& hb, int prec,
+                            hipStream_t s)
+{
+    // one single-trajectory group per batch with a vacuum phase: T = 0, no
+    // jumps, vacuum_steps steps, final state out
+    std::vector<HostBatch> vb;
+    std::vector<size_t> which, off;
+    size_t total = 0;
+    for (size_t i = 0; i < hb.size(); ++i) {
+        if (hb[i]->vacuum_steps <= 0) continue;
+        HostBatch v = *hb[i];
+        v.batch.n_traj = 1;
+        v.batch.no_jump_shortcut = 0;
+        v.phys.do_jumps = 0;
+        v.tau = {0.0, 1.0};
+        v.T = {0.0, 0.0};
+        v.tau_start = 0.0;
+        v.n_steps = hb[i]->vacuum_steps;
+        v.vacuum_steps = 0;
+        v.zeroth = qt_results{};
+        vb.push_back(v);
+        which.push_back(i);
+        off.push_back(total);
+        total += 2 * (size_t)v.phys.N;
+    }
+    if (vb.empty()) return QT_OK;
+    double* psi = nullptr;
+    QT_HIP(hipMalloc(reinterpret_cast<void**>(&psi), total * sizeof(double)));
+    std::vector<const HostBatch*> v;
+    std::vector<qt_results> outs(vb.size());
+    for (size_t k = 0; k < vb.size(); ++k) {
+        v.push_back(&vb[k]);
+        std::memset(&outs[k], 0, sizeof(qt_results));
+        outs[k].psi = psi + off[k];
+    }
+    qt_status st = run_fused_groups(ctx, v, outs, prec, s);
+    std::vector<double> host(total);
+    if (st == QT_OK) {
+        hipError_t e = hipMemcpyAsync(host.data(), psi, total * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(QT_EDEVICE, "vacuum phase: %s", hipGetErrorString(e));
+    }
+    hipFree(psi);
+    if (st != QT_OK) return st;
+    for (size_t k = 0; k < vb.size(); ++k) {
+        HostBatch& h = *hb[which[k]];
+        auto t = std::make_shared<InitTable>();
+        t->psi.assign(host.begin() + off[k], host.begin() + off[k] + 2 * (size_t)h.phys.N);
+        for (int q = 0; q < 6; ++q) t->overlap[q] = h.init->overlap[q];   // prepared state
+        h.init = t;
+    }
+    return QT_OK;
+}
+
+qt_status run_zeroth_trajectories(qt_context* ctx, const std::vector<HostBatch*>& hb, int prec,
+                                  hipStream_t s, void** mem)
+{
+    *mem = nullptr;
+    std::vector<HostBatch> zb;
+    std::vector<size_t> which, off;
+    // per zeroth trajectory: 16 doubles (norm, first_r, 6 overlaps, 6
+    // survivals, mean_r, min_gap), 4 int32, 1 int64, then psi (2N doubles)
+    size_t total = 0;
+    for (size_t i = 0; i < hb.size(); ++i) {
+        if (!hb[i]->batch.no_jump_shortcut || !hb[i]->phys.do_jumps) continue;
+        HostBatch z = *hb[i];
+        z.batch.n_traj = 1;
+        z.batch.no_jump_shortcut = 0;
+        z.phys.flags |= kFlagZeroth;
+        z.zeroth = qt_results{};
+        zb.push_back(z);
+        which.push_back(i);
+        off.push_back(total);
+        total += 16 * 8 + 16 + 8 + 2 * (size_t)z.phys.N * 8;
+    }
+    if (zb.empty()) return QT_OK;
+    char* base = nullptr;
+    QT_HIP(hipMallocAsync(reinterpret_cast<void**>(&base), total, s));
+    std::vector<const HostBatch*> v;
+    std::vector<qt_results> outs(zb.size());
+    for (size_t k = 0; k < zb.size(); ++k) {
+        v.push_back(&zb[k]);
+        double* d = reinterpret_cast<double*>(base + off[k]);
+        int32_t* i4 = reinterpret_cast<int32_t*>(d + 16);
+        qt_results& r = outs[k];
+        r.norm = d; r.first_r = d + 1; r.overlap = d + 2; r.survival = d + 8;
+        r.mean_r = d + 14; r.min_gap = d + 15;
+        r.l = i4; r.color = i4 + 1; r.n_jumps = i4 + 2; r.status = i4 + 3;
+        r.steps_done = reinterpret_cast<int64_t*>(i4 + 4);
+        r.psi = reinterpret_cast<double*>(i4 + 6);
+    }
+    qt_status st = run_fused_groups(ctx, v, outs, prec, s);
+    std::vector<double> gap(zb.size());
+    for (size_t k = 0; st == QT_OK && k < zb.size(); ++k) {
+        if (hipMemcpyAsync(&gap[k], outs[k].min_gap, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            st = fail(QT_EDEVICE, "zeroth trajectory: copy failed");
+    }
+    if (st == QT_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(QT_EDEVICE, "zeroth trajectory failed");
+    if (st != QT_OK) {
+        hipFreeAsync(base, s);
+        return st;
+    }
+    for (size_t k = 0; k < zb.size(); ++k) {
+        hb[which[k]]->zeroth = outs[k];
+        hb[which[k]]->r_min = gap[k];    // threshold 0: the smallest gap is the smallest norm
+    }
+    *mem = base;
+    return QT_OK;
+}
+
 }  // namespace qt
 
 extern "C" {
@@ -829,10 +947,16 @@ qt_status qt_run(qt_context* ctx, const qt_physics* phys, const qt_ttable* tt, c
     qt_status st = prepare(phys, tt, init, batch, &hb);
     if (st != QT_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::vector<HostBatch*> hv{&hb};
+    if ((st = run_vacuum_phases(ctx, hv, batch->precision, s)) != QT_OK) return st;
     if (batch->form == QT_FORM_PLAIN) return run_plain(ctx, hb, *dev_out, s);
+    void* zmem = nullptr;
+    if ((st = run_zeroth_trajectories(ctx, hv, batch->precision, s, &zmem)) != QT_OK) return st;
     std::vector<const HostBatch*> v{&hb};
     std::vector<qt_results> outs{*dev_out};
-    return run_fused_groups(ctx, v, outs, batch->precision, s);
+    st = run_fused_groups(ctx, v, outs, batch->precision, s);
+    if (zmem) hipFreeAsync(zmem, s);
+    return st;
 }
 
 qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys,
@@ -850,13 +974,22 @@ qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys
         if (batch[i].form != QT_FORM_FUSED) return fail(QT_EINVAL, "batch %d: qt_run_many runs the fused form", i);
         if (batch[i].precision != batch[0].precision) return fail(QT_EINVAL, "batch %d: mixed precision", i);
     }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    std::vector<HostBatch*> hv;
+    for (auto& h : hbs) hv.push_back(&h);
+    qt_status st = run_vacuum_phases(ctx, hv, batch[0].precision, s);
+    void* zmem = nullptr;
+    if (st == QT_OK) st = run_zeroth_trajectories(ctx, hv, batch[0].precision, s, &zmem);
+    if (st != QT_OK) return st;
     std::vector<const HostBatch*> v;
     std::vector<qt_results> outs;
     for (int i = 0; i < n_batches; ++i) {
         v.push_back(&hbs[i]);
         outs.push_back(dev_out[i]);
     }
-    return run_fused_groups(ctx, v, outs, batch[0].precision, static_cast<hipStream_t>(hip_stream));
+    st = run_fused_groups(ctx, v, outs, batch[0].precision, s);
+    if (zmem) hipFreeAsync(zmem, s);
+    return st;
 }
 
 qt_status qt_plan(qt_context* ctx, int32_t N, int32_t precision, int32_t tune,

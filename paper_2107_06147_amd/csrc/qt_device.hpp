@@ -117,14 +117,6 @@ __device__ __forceinline__ int opaque_lane(int t)
     return t;
 }
 
-// Value select (a select between two array elements written as an lvalue
-// conditional would select addresses and push the arrays out of registers).
-template <class R>
-__device__ __forceinline__ cx<R> pick(bool c, cx<R> x, cx<R> y)
-{
-    return mk(c ? x.re : y.re, c ? x.im : y.im);
-}
-
 // LDS index with one pad element every 16 (spreads power-of-two strides
 // over the banks).
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }

@@ -60,6 +60,9 @@ struct HostBatch {
     std::shared_ptr<const std::vector<double>> kin;     // 2N: (2/N) exp(-i E_k dt)
     std::shared_ptr<const std::vector<double>> basis;   // 6N
     std::shared_ptr<const InitTable> init;
+    int64_t vacuum_steps = 0;       // in-vacuum steps before the medium (once)
+    qt_results zeroth{};            // device results of the zeroth trajectory
+    double r_min = 0;               // its smallest norm
 };
 
 qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in,
@@ -97,6 +100,18 @@ qt_status copy_results(const qt_results& src, const qt_results& dst, int64_t n, 
                        hipStream_t s);
 qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb,
                            const std::vector<qt_results>& outs, int prec, hipStream_t s);
+
+// Runs the in-vacuum phase (T = 0, no jumps, vacuum_steps steps) of every
+// batch that has one, all in one launch, and makes its result the batch's
+// initial state.  Synchronises `s`.
+qt_status run_vacuum_phases(qt_context* ctx, const std::vector<HostBatch*>& hb, int prec,
+                            hipStream_t s);
+// Runs the zeroth (no-jump) trajectory of every batch that asks for the
+// no-jump shortcut, all in one launch; sets each such batch's `zeroth`
+// (device results, held in *mem, which the caller frees stream-ordered after
+// its launch) and `r_min`.  Synchronises `s`.
+qt_status run_zeroth_trajectories(qt_context* ctx, const std::vector<HostBatch*>& hb, int prec,
+                                  hipStream_t s, void** mem);
 
 // LPT order of (group, index) items: longest remaining work first.
 void build_items(const std::vector<const HostBatch*>& hb, std::vector<int32_t>* ig,

@@ -36,7 +36,15 @@ struct GroupDesc {
     qt_results out;           // device pointers
     void*      st_psi;        // n_traj * N complex (segmented runs), or null
     TrajState* st;            // n_traj records (segmented runs), or null
+    qt_results zeroth;        // no-jump trajectory's results (one entry, with
+                              // psi), or all null: no shortcut
+    double     r_min;         // its smallest norm; thresholds below take it
 };
+
+// Internal flag (above the public QT_FLAG_* bits): the group is the zeroth
+// trajectory of a batch, threshold 0 (it never jumps; its smallest gap is its
+// smallest norm).
+constexpr int32_t kFlagZeroth = 1 << 16;
 
 struct FusedArgs {
     const GroupDesc* groups;

@@ -107,6 +107,12 @@ qt_status qt_job_create(qt_context* ctx, const qt_physics* phys, const qt_ttable
     j->ctx = ctx;
     qt_status st = prepare(phys, tt, init, batch, &j->hb);
     if (st == QT_OK && batch->form != QT_FORM_FUSED) st = fail(QT_EINVAL, "jobs run the fused form");
+    if (st == QT_OK && batch->no_jump_shortcut)
+        st = fail(QT_EINVAL, "the no-jump shortcut is not available in segmented jobs");
+    if (st == QT_OK) {
+        std::vector<HostBatch*> hv{&j->hb};
+        st = run_vacuum_phases(ctx, hv, batch->precision, nullptr);
+    }
     if (st != QT_OK) {
         delete j;
         return st;

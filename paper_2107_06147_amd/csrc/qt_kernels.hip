@@ -348,6 +348,37 @@ __device__ __forceinline__ void write_results(const GroupDesc& g, int64_t idx, c
     }
 }
 
+// Results of a trajectory that cannot jump: those of the batch's zeroth
+// trajectory (paper: Sec. "Summary of QTraj execution", step 4, r_0 < rMin),
+// with its own first threshold r and gap r_min - r (its gap to every norm of
+// that evolution, the smallest being at the smallest norm).
+template <int N, int W>
+__device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, double r)
+{
+    const qt_results& z = g.zeroth;
+    const qt_results& o = g.out;
+    if (threadIdx.x == 0) {
+        if (o.norm) o.norm[idx] = z.norm[0];
+        if (o.first_r) o.first_r[idx] = r;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            if (o.overlap) o.overlap[6 * idx + q] = z.overlap[q];
+            if (o.survival) o.survival[6 * idx + q] = z.survival[q];
+        }
+        if (o.mean_r) o.mean_r[idx] = z.mean_r[0];
+        if (o.l) o.l[idx] = z.l[0];
+        if (o.color) o.color[idx] = z.color[0];
+        if (o.n_jumps) o.n_jumps[idx] = 0;
+        if (o.status) o.status[idx] = QT_TRAJ_NOJUMP;
+        if (o.steps_done) o.steps_done[idx] = z.steps_done[0];
+        if (o.min_gap) o.min_gap[idx] = g.r_min - r;
+    }
+    if (o.psi) {
+        double* dst = o.psi + (size_t)idx * 2 * N;
+        for (int m = threadIdx.x; m < 2 * N; m += W) dst[m] = z.psi[m];
+    }
+}
+
 // ------------------------------------------------------------ FUSED -------
 
 template <class R, int N, int W>
@@ -399,6 +430,15 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
             l = s.l; c = s.c; n_jumps = s.n_jumps; status = s.status; step = s.step;
             r = s.r; first_r = s.first_r; min_gap = s.min_gap; norm = s.norm;
         } else {
+            // the zeroth trajectory of a batch has threshold 0: it never jumps
+            const U4 e0 = event_block(g.seed, traj_id, 0);
+            r = uniform(g.flags & kFlagZeroth ? 0.0 : uniform01(e0.w[2]));
+            if (g.zeroth.norm != nullptr && r < g.r_min) {
+                // below every norm of the no-jump evolution: this trajectory
+                // is that evolution
+                take_zeroth<N, W>(g, idx, r);
+                continue;
+            }
             sfor<0, R1>([&](auto Rr) QT_INL {
                 const int ma = ln.ja + Rr * T, mb = ln.jb + Rr * T;
                 a[Rr] = mk(R(g.init_psi[2 * ma]), R(g.init_psi[2 * ma + 1]));
@@ -407,8 +447,6 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
             });
             l = g.init_l; c = g.init_color; n_jumps = 0; status = QT_TRAJ_OK; step = 0;
             min_gap = __builtin_huge_val();
-            const U4 e0 = event_block(g.seed, traj_id, 0);
-            r = uniform01(e0.w[2]);
             first_r = r;
             norm = g.dr * block_sum<W>(sum_abs2<R, N, W>(a, b), red);
             if (g.do_jumps && r > g.r_max) status = QT_TRAJ_RMAX;

@@ -97,6 +97,8 @@ qt_status admit(qt_server* s, Request& q)
     std::vector<qt_results> outs{q.res.r};
     {
         std::lock_guard<std::mutex> lk(s->ctx->mu);   // the context's table caches
+        std::vector<HostBatch*> hv{&q.hb};
+        if ((st = run_vacuum_phases(s->ctx, hv, prec, s->stream)) != QT_OK) return st;
         if ((st = upload_groups(s->ctx, hbv, prec, outs, false, s->stream, false, &q.dg)) != QT_OK)
             return st;
     }
@@ -361,6 +363,7 @@ qt_status qt_submit(qt_server* s, const qt_physics* phys, const qt_ttable* tt, c
     auto q = std::make_shared<Request>();
     qt_status st = prepare(phys, tt, init, batch, &q->hb);
     if (st != QT_OK) return st;
+    if (batch->no_jump_shortcut) return fail(QT_EINVAL, "the no-jump shortcut is not available in the server");
     if (batch->precision != s->cfg.precision) return fail(QT_EINVAL, "request precision differs from the server's");
     if (batch->form != QT_FORM_FUSED) return fail(QT_EINVAL, "the server runs the fused form");
     if (request_bytes(q->hb, s->cfg.precision) > s->budget)

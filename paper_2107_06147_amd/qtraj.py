@@ -24,7 +24,7 @@ QT_FP64, QT_FP32_BULK = 0, 1
 QT_FORM_FUSED, QT_FORM_PLAIN = 0, 1
 QT_INIT_COULOMB, QT_INIT_GAUSSIAN, QT_INIT_ARRAY = 0, 1, 2
 QT_SINGLET, QT_OCTET = 0, 1
-QT_TRAJ_OK, QT_TRAJ_RMAX, QT_TRAJ_MAXJUMPS = 0, 1, 2
+QT_TRAJ_OK, QT_TRAJ_RMAX, QT_TRAJ_MAXJUMPS, QT_TRAJ_LMAX, QT_TRAJ_NOJUMP = 0, 1, 2, 3, 4
 QT_FLAG_KINETIC_OFF = 1
 
 _D = C.POINTER(C.c_double)
@@ -41,7 +41,8 @@ class qt_physics(C.Structure):
 
 class qt_ttable(C.Structure):
     _fields_ = [("tau", _D), ("T", _D), ("n", C.c_int32), ("tau_start", C.c_double),
-                ("T_final", C.c_double), ("max_steps", C.c_int64)]
+                ("T_final", C.c_double), ("max_steps", C.c_int64),
+                ("vacuum_steps", C.c_int64)]
 
 
 class qt_init(C.Structure):
@@ -51,7 +52,8 @@ class qt_init(C.Structure):
 
 class qt_batch(C.Structure):
     _fields_ = [("n_traj", C.c_int64), ("seed", C.c_uint64), ("traj_id0", C.c_uint64),
-                ("traj_id_stride", C.c_uint64), ("precision", C.c_int32), ("form", C.c_int32)]
+                ("traj_id_stride", C.c_uint64), ("precision", C.c_int32), ("form", C.c_int32),
+                ("no_jump_shortcut", C.c_int32)]
 
 
 class qt_results(C.Structure):
@@ -156,7 +158,8 @@ def ttable(cfg, keep):
     T = np.ascontiguousarray(cfg["T"], dtype=np.float64)
     keep += [tau, T]
     return qt_ttable(_dp(tau), _dp(T), len(tau), float(cfg["tau_start"]),
-                     float(cfg.get("T_final", 0.0)), int(cfg.get("max_steps", 2**62)))
+                     float(cfg.get("T_final", 0.0)), int(cfg.get("max_steps", 2**62)),
+                     int(cfg.get("vacuum_steps", 0)))
 
 
 def init(cfg, keep):
@@ -175,7 +178,8 @@ def init(cfg, keep):
 def batch(cfg, precision, form=QT_FORM_FUSED, n_traj=None, traj_id0=None):
     return qt_batch(int(cfg["n_traj"] if n_traj is None else n_traj), int(cfg.get("seed", 1)),
                     int(cfg.get("traj_id0", 0) if traj_id0 is None else traj_id0),
-                    int(cfg.get("traj_id_stride", 1)), int(precision), int(form))
+                    int(cfg.get("traj_id_stride", 1)), int(precision), int(form),
+                    int(cfg.get("no_jump_shortcut", 0)))
 
 
 def alloc_results(n, N, want_psi, device="cuda"):

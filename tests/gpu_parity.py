@@ -24,6 +24,8 @@ FP64_DELTA = 1e-9
 # FP32-bulk: per-step rounding of O(1e-7) accumulated over up to 1e3 steps
 FP32_TOL = dict(psi=3e-4, norm=3e-5, overlap=3e-5, mean_r=3e-4)
 FP32_DELTA = 1e-4
+# relative bound on survival ratios whose initial overlap is nearly cancelled
+SV_REL = {qt.QT_FP64: 1e-7, qt.QT_FP32_BULK: 1e-3}
 
 
 def gpu_run(ctx, cfg, precision, form=qt.QT_FORM_FUSED, want_psi=True, n_traj=None,
@@ -47,7 +49,8 @@ def compare(ref, out, precision, check_psi=True, label=""):
     for i in range(n):
         if near[i]:
             # valid, not necessarily identical
-            assert out["status"][i] in (qt.QT_TRAJ_OK, qt.QT_TRAJ_RMAX, qt.QT_TRAJ_MAXJUMPS)
+            assert out["status"][i] in (qt.QT_TRAJ_OK, qt.QT_TRAJ_RMAX, qt.QT_TRAJ_MAXJUMPS,
+                                        qt.QT_TRAJ_NOJUMP)
             assert 0.0 <= out["norm"][i] <= 1.0 + 1e-6
             continue
         for key in ("status", "n_jumps", "l", "color", "steps_done"):
@@ -55,10 +58,19 @@ def compare(ref, out, precision, check_psi=True, label=""):
         e_norm = abs(out["norm"][i] - ref["norm"][i])
         # survival = overlap / initial overlap is compared on the scale of
         # the overlap, |d survival| * initial overlap: a ratio to a small
-        # initial overlap magnifies the (absolute) overlap error
+        # initial overlap magnifies the (absolute) overlap error.  Where the
+        # initial overlap itself is nearly cancelled (an analytic state
+        # almost orthogonal to the initial one on the grid), its relative
+        # rounding, ~1e-16 times the ratio of the summed terms to the sum,
+        # also passes into the ratio: each side builds the Coulomb states
+        # with its own code, so such a survival is held to a relative bound
+        # (SV_REL) when the overlap-scale bound does not hold.
         ov_r, sv_r = ref["overlap"][i], ref["survival"][i]
         init_ov = np.where(sv_r != 0, ov_r / np.where(sv_r != 0, sv_r, 1.0), 1.0)
-        e_sv = np.max(np.abs(out["survival"][i] - sv_r) * np.minimum(init_ov, 1.0))
+        d_sv = np.abs(out["survival"][i] - sv_r)
+        e_sv = d_sv * np.minimum(init_ov, 1.0)
+        rel_ok = d_sv <= SV_REL[precision] * np.abs(sv_r)
+        e_sv = np.max(np.where(rel_ok, 0.0, e_sv))
         e_ov = max(np.max(np.abs(out["overlap"][i] - ov_r)), e_sv)
         e_mr = abs(out["mean_r"][i] - ref["mean_r"][i]) / max(abs(ref["mean_r"][i]), 1e-300)
         stats["norm"] = max(stats["norm"], e_norm)

@@ -1,0 +1,111 @@
+"""The zeroth (no-jump) trajectory with the rMin shortcut, and the in-vacuum
+evolution before the medium, on the GPU against the oracle and against the
+GPU's own full evolution.  Marked `gpu`."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_06147_amd import qtraj as qt
+from paper_2107_06147_amd import workloads as W
+from tests.gpu_parity import compare, gpu_run
+
+pytestmark = pytest.mark.gpu
+
+F64, F32 = qt.QT_FP64, qt.QT_FP32_BULK
+FUSED, PLAIN = qt.QT_FORM_FUSED, qt.QT_FORM_PLAIN
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = qt.Context(0)
+    yield c
+    c.close()
+
+
+def _cfg(**kw):
+    base = dict(N=512, L=20.0, dt=0.002, kappa_hat=4.0, gamma_hat=-1.0, n_traj=96, seed=3,
+                init_kind=W.INIT_COULOMB)
+    base.update(kw)
+    return W.base(**base, **W.constant_T(0.35, 500))
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_shortcut_equals_full_evolution(ctx, prec):
+    """Trajectories below the zeroth trajectory's smallest norm take its
+    results: bit for bit what their own evolution gives; the others are
+    untouched."""
+    cfg = _cfg()
+    full = gpu_run(ctx, cfg, prec)
+    fast = gpu_run(ctx, dict(cfg, no_jump_shortcut=1), prec)
+    took = fast["status"] == qt.QT_TRAJ_NOJUMP
+    print("shortcut", prec, int(took.sum()), "of", len(took))
+    assert 0 < took.sum() < len(took)
+    assert np.all(full["n_jumps"][took] == 0) and np.all(full["status"][took] == 0)
+    for k in full:
+        if k != "status":
+            assert np.array_equal(full[k], fast[k]), k
+    assert np.array_equal(full["status"][~took], fast["status"][~took])
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_shortcut_against_oracle(ctx, prec):
+    """The same shortcut on both sides: the same trajectories take it (away
+    from the threshold) and every result matches to the parity bar."""
+    cfg = dict(_cfg(n_traj=24), no_jump_shortcut=1)
+    ref = oracle.run(cfg, want_psi=True)
+    out = gpu_run(ctx, cfg, prec)
+    err = compare(ref, out, prec, label="shortcut")
+    print("shortcut parity", prec, err)
+    # the shortcut decision compares the threshold with the zeroth's
+    # smallest norm; away from that norm both sides decide alike
+    r_min = np.min(ref["norm"][ref["status"] == oracle.STATUS_NOJUMP], initial=np.inf)
+    tol = 1e-9 if prec == F64 else 1e-4
+    clear = np.abs(ref["first_r"] - r_min) > tol
+    assert np.array_equal((ref["status"] == oracle.STATUS_NOJUMP)[clear],
+                          (out["status"] == qt.QT_TRAJ_NOJUMP)[clear])
+
+
+def test_shortcut_rejected_where_unavailable(ctx):
+    cfg = dict(_cfg(n_traj=4), no_jump_shortcut=1)
+    with pytest.raises(qt.QtError):
+        qt.run(ctx, cfg, precision=F64, form=PLAIN)
+    with pytest.raises(qt.QtError):
+        qt.Job(ctx, cfg, precision=F32, segment_steps=50)
+    srv = qt.Server(ctx, precision=F32, segment_steps=50)
+    try:
+        with pytest.raises(qt.QtError):
+            srv.submit(cfg)
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("prec,form", [(F64, FUSED), (F64, PLAIN), (F32, FUSED)])
+def test_vacuum_phase_against_oracle(ctx, prec, form):
+    """300 in-vacuum steps of a Gaussian l = 1 state, then 250 medium steps
+    with jumps: every trajectory matches the oracle."""
+    cfg = W.base(N=512, L=20.0, dt=0.002, kappa_hat=4.0, gamma_hat=-1.0, n_traj=12, seed=4,
+                 init_kind=W.INIT_GAUSSIAN, init_width=1.2, init_l=1, vacuum_steps=300,
+                 **W.constant_T(0.4, 250))
+    ref = oracle.run(cfg, want_psi=True)
+    out = gpu_run(ctx, cfg, prec, form=form)
+    print("vacuum parity", prec, form, compare(ref, out, prec, label="vacuum"))
+
+
+def test_vacuum_phase_in_job_and_many(ctx):
+    """A job and qt_run_many start from the same stored vacuum state as
+    qt_run: bitwise equal results."""
+    import torch
+    cfg = W.base(N=512, L=20.0, dt=0.002, kappa_hat=6.0, n_traj=20, seed=9,
+                 init_kind=W.INIT_GAUSSIAN, init_width=1.0, vacuum_steps=150,
+                 **W.constant_T(0.45, 200))
+    alone = gpu_run(ctx, cfg, F32)
+    job = qt.Job(ctx, cfg, precision=F32, segment_steps=64)
+    job.advance(10**6)
+    res = qt.to_numpy(job.results(want_psi=True))
+    job.close()
+    many = qt.run_many(ctx, [cfg, dict(cfg, seed=10)], precision=F32, want_psi=True)
+    torch.cuda.synchronize()
+    m0 = qt.to_numpy(many[0])
+    for k in alone:
+        assert np.array_equal(alone[k], res[k]), k
+        assert np.array_equal(alone[k], m0[k]), k
