@@ -110,6 +110,31 @@ def profile_mode(args):
     ctx.close()
 
 
+def shortcut_leg(ctx, qt, runs, out, torch):
+    """The N=2048 batch (kappa_hat = 1 and 4, gamma_hat = 0) with the
+    zeroth-trajectory shortcut: trajectories whose first threshold lies below
+    the no-jump evolution's smallest norm are not evolved.  Reports the share
+    that cannot jump and the time against the full run (the headline value
+    never uses the shortcut)."""
+    rep = {}
+    for run in (runs[0], runs[2]):
+        times = {}
+        for name, c in (("full", run), ("shortcut", dict(run, no_jump_shortcut=1))):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            qt.run(ctx, c, precision=qt.QT_FP32_BULK, out=out)
+            torch.cuda.synchronize()
+            times[name] = time.perf_counter() - t0
+        nojump = int((out["status"] == qt.QT_TRAJ_NOJUMP).sum().item())
+        steps = int(out["steps_done"].sum().item())
+        rep["kappa_hat_%g" % run["kappa_hat"]] = {
+            "trajectories": int(run["n_traj"]), "cannot_jump": nojump,
+            "wall_s_full": times["full"], "wall_s_shortcut": times["shortcut"],
+            "speedup": times["full"] / times["shortcut"],
+            "equivalent_traj_steps_per_s": steps / times["shortcut"]}
+    return rep
+
+
 def uneven_leg(ctx, qt, W, torch):
     """The uneven batch: 16,384 trajectories with their own N (1024, 2048 or
     4096), l and temperature history, in one persistent launch per N."""
@@ -222,6 +247,7 @@ def main():
     extra["plan"] = {"fp32_threads_per_traj": w32, "fp32_traj_per_cu": s32,
                      "fp64_threads_per_traj": w64, "fp64_traj_per_cu": s64}
 
+    extra["c2_no_jump_shortcut"] = shortcut_leg(ctx, qt, runs, out32, torch)
     if not args.no_c3:
         extra["c3_uneven"] = uneven_leg(ctx, qt, W, torch)
     if args.c5:

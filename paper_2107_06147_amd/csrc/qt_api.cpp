@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "qt_host.hpp"
+#include "qt_philox.h"
 
 namespace {
 thread_local std::string g_last_error;
@@ -131,6 +132,10 @@ qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in, 
         return fail(QT_EINVAL, "no_jump_shortcut must be 0 or 1");
     if (b->no_jump_shortcut && b->form != QT_FORM_FUSED)
         return fail(QT_EINVAL, "the no-jump shortcut runs in the fused form");
+    // the rMin test precedes the rMax test; rMin is known only once the
+    // zeroth trajectory has run, so the shortcut needs rMax = 1
+    if (b->no_jump_shortcut && p->r_max != 1.0)
+        return fail(QT_EINVAL, "the no-jump shortcut needs r_max = 1");
     return QT_OK;
 }
 
@@ -500,7 +505,7 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         d.st_psi = nullptr;
         d.st = nullptr;
         d.zeroth = h.zeroth;
-        d.r_min = h.r_min;
+        d.zdone = h.zdone;
         dg->host[g] = d;
         std::memcpy(&blob[o[g].tau], h.tau.data(), h.tau.size() * 8);
         std::memcpy(&blob[o[g].T], h.T.data(), h.T.size() * 8);
@@ -537,17 +542,32 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
 void build_items(const std::vector<const HostBatch*>& hb, std::vector<int32_t>* ig,
                  std::vector<int64_t>* ii)
 {
-    struct It { double cost; int32_t g; int64_t i; };
+    struct It { double cost; double r; int32_t g; int64_t i; };
     std::vector<It> v;
     size_t total = 0;
     for (const HostBatch* h : hb) total += (size_t)h->batch.n_traj;
     v.reserve(total);
     for (size_t g = 0; g < hb.size(); ++g) {
         const HostBatch& h = *hb[g];
-        const double cost = (double)h.n_steps * h.phys.N * std::log2((double)h.phys.N);
-        for (int64_t i = 0; i < h.batch.n_traj; ++i) v.push_back({cost, (int32_t)g, i});
+        // a batch's zeroth trajectory goes first: the sooner it finishes, the
+        // more of its batch can take its results
+        const double cost = (h.phys.flags & kFlagZeroth)
+                                ? HUGE_VAL
+                                : (double)h.n_steps * h.phys.N * std::log2((double)h.phys.N);
+        const bool order_by_r = h.zeroth.norm != nullptr;
+        const uint64_t stride = h.batch.traj_id_stride ? h.batch.traj_id_stride : 1u;
+        for (int64_t i = 0; i < h.batch.n_traj; ++i) {
+            // with the no-jump shortcut, the lowest first thresholds (the
+            // trajectories that may take the zeroth's results) go last
+            double r = 1.0;
+            if (order_by_r)
+                r = uniform01(event_block(h.batch.seed, h.batch.traj_id0 + (uint64_t)i * stride, 0).w[2]);
+            v.push_back({cost, r, (int32_t)g, i});
+        }
     }
-    std::stable_sort(v.begin(), v.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
+    std::stable_sort(v.begin(), v.end(), [](const It& a, const It& b) {
+        return a.cost > b.cost || (a.cost == b.cost && a.r > b.r);
+    });
     ig->resize(v.size());
     ii->resize(v.size());
     for (size_t k = 0; k < v.size(); ++k) {
@@ -877,57 +897,54 @@ qt_status run_vacuum_phases(qt_context* ctx, const std::vector<HostBatch*>& hb, 
     return QT_OK;
 }
 
-qt_status run_zeroth_trajectories(qt_context* ctx, const std::vector<HostBatch*>& hb, int prec,
-                                  hipStream_t s, void** mem)
+qt_status add_zeroth_groups(const std::vector<HostBatch*>& hb, std::vector<HostBatch>* zb,
+                            std::vector<const HostBatch*>* v, std::vector<qt_results>* outs,
+                            hipStream_t s, void** mem)
 {
     *mem = nullptr;
-    std::vector<HostBatch> zb;
-    std::vector<size_t> which, off;
-    // per zeroth trajectory: 16 doubles (norm, first_r, 6 overlaps, 6
-    // survivals, mean_r, min_gap), 4 int32, 1 int64, then psi (2N doubles)
-    size_t total = 0;
-    for (size_t i = 0; i < hb.size(); ++i) {
-        if (!hb[i]->batch.no_jump_shortcut || !hb[i]->phys.do_jumps) continue;
-        HostBatch z = *hb[i];
-        z.batch.n_traj = 1;
-        z.batch.no_jump_shortcut = 0;
-        z.phys.flags |= kFlagZeroth;
-        z.zeroth = qt_results{};
-        zb.push_back(z);
-        which.push_back(i);
+    size_t nz = 0;
+    for (HostBatch* h : hb)
+        if (h->batch.no_jump_shortcut && h->phys.do_jumps) ++nz;
+    if (nz == 0) return QT_OK;
+    // [nz completion flags | per zeroth: 16 doubles (norm, first_r, 6
+    // overlaps, 6 survivals, mean_r, min_gap), 4 int32, 1 int64, psi (2N)]
+    std::vector<size_t> off;
+    size_t total = 256;
+    for (HostBatch* h : hb) {
+        if (!h->batch.no_jump_shortcut || !h->phys.do_jumps) continue;
         off.push_back(total);
-        total += 16 * 8 + 16 + 8 + 2 * (size_t)z.phys.N * 8;
+        total += 16 * 8 + 16 + 8 + 2 * (size_t)h->phys.N * 8;
+        total = (total + 255) & ~(size_t)255;
     }
-    if (zb.empty()) return QT_OK;
+    total += ((nz * 4 + 255) & ~(size_t)255);
     char* base = nullptr;
     QT_HIP(hipMallocAsync(reinterpret_cast<void**>(&base), total, s));
-    std::vector<const HostBatch*> v;
-    std::vector<qt_results> outs(zb.size());
-    for (size_t k = 0; k < zb.size(); ++k) {
-        v.push_back(&zb[k]);
+    int32_t* flags = reinterpret_cast<int32_t*>(base + total - ((nz * 4 + 255) & ~(size_t)255));
+    QT_HIP(launch_zero_i32(flags, (int64_t)nz, s));
+    zb->reserve(nz);
+    size_t k = 0;
+    for (HostBatch* h : hb) {
+        if (!h->batch.no_jump_shortcut || !h->phys.do_jumps) continue;
         double* d = reinterpret_cast<double*>(base + off[k]);
         int32_t* i4 = reinterpret_cast<int32_t*>(d + 16);
-        qt_results& r = outs[k];
+        qt_results r{};
         r.norm = d; r.first_r = d + 1; r.overlap = d + 2; r.survival = d + 8;
         r.mean_r = d + 14; r.min_gap = d + 15;
         r.l = i4; r.color = i4 + 1; r.n_jumps = i4 + 2; r.status = i4 + 3;
         r.steps_done = reinterpret_cast<int64_t*>(i4 + 4);
         r.psi = reinterpret_cast<double*>(i4 + 6);
-    }
-    qt_status st = run_fused_groups(ctx, v, outs, prec, s);
-    std::vector<double> gap(zb.size());
-    for (size_t k = 0; st == QT_OK && k < zb.size(); ++k) {
-        if (hipMemcpyAsync(&gap[k], outs[k].min_gap, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
-            st = fail(QT_EDEVICE, "zeroth trajectory: copy failed");
-    }
-    if (st == QT_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(QT_EDEVICE, "zeroth trajectory failed");
-    if (st != QT_OK) {
-        hipFreeAsync(base, s);
-        return st;
-    }
-    for (size_t k = 0; k < zb.size(); ++k) {
-        hb[which[k]]->zeroth = outs[k];
-        hb[which[k]]->r_min = gap[k];    // threshold 0: the smallest gap is the smallest norm
+        HostBatch z = *h;
+        z.batch.n_traj = 1;
+        z.batch.no_jump_shortcut = 0;
+        z.phys.flags |= kFlagZeroth;
+        z.zeroth = qt_results{};
+        z.zdone = flags + k;
+        zb->push_back(z);
+        v->push_back(&zb->back());
+        outs->push_back(r);
+        h->zeroth = r;
+        h->zdone = flags + k;
+        ++k;
     }
     *mem = base;
     return QT_OK;
@@ -950,10 +967,11 @@ qt_status qt_run(qt_context* ctx, const qt_physics* phys, const qt_ttable* tt, c
     std::vector<HostBatch*> hv{&hb};
     if ((st = run_vacuum_phases(ctx, hv, batch->precision, s)) != QT_OK) return st;
     if (batch->form == QT_FORM_PLAIN) return run_plain(ctx, hb, *dev_out, s);
-    void* zmem = nullptr;
-    if ((st = run_zeroth_trajectories(ctx, hv, batch->precision, s, &zmem)) != QT_OK) return st;
     std::vector<const HostBatch*> v{&hb};
     std::vector<qt_results> outs{*dev_out};
+    std::vector<HostBatch> zb;
+    void* zmem = nullptr;
+    if ((st = add_zeroth_groups(hv, &zb, &v, &outs, s, &zmem)) != QT_OK) return st;
     st = run_fused_groups(ctx, v, outs, batch->precision, s);
     if (zmem) hipFreeAsync(zmem, s);
     return st;
@@ -978,8 +996,6 @@ qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys
     std::vector<HostBatch*> hv;
     for (auto& h : hbs) hv.push_back(&h);
     qt_status st = run_vacuum_phases(ctx, hv, batch[0].precision, s);
-    void* zmem = nullptr;
-    if (st == QT_OK) st = run_zeroth_trajectories(ctx, hv, batch[0].precision, s, &zmem);
     if (st != QT_OK) return st;
     std::vector<const HostBatch*> v;
     std::vector<qt_results> outs;
@@ -987,6 +1003,9 @@ qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys
         v.push_back(&hbs[i]);
         outs.push_back(dev_out[i]);
     }
+    std::vector<HostBatch> zb;
+    void* zmem = nullptr;
+    if ((st = add_zeroth_groups(hv, &zb, &v, &outs, s, &zmem)) != QT_OK) return st;
     st = run_fused_groups(ctx, v, outs, batch[0].precision, s);
     if (zmem) hipFreeAsync(zmem, s);
     return st;

@@ -17,6 +17,8 @@
 #include <stdint.h>
 #include <type_traits>
 
+#include "qt_philox.h"
+
 namespace qt {
 
 // ---------------------------------------------------------------- basics --
@@ -601,39 +603,6 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const 
         });
     }
     __syncthreads();
-}
-
-// --------------------------------------------------------------- Philox ---
-
-struct U4 { uint64_t w[4]; };
-
-__device__ __forceinline__ U4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                            uint64_t k0, uint64_t k1)
-{
-    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-#pragma unroll
-    for (int i = 0; i < 10; ++i) {
-        const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
-        const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
-        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-        k0 += W0; k1 += W1;
-    }
-    U4 o;
-    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
-    return o;
-}
-
-__device__ __forceinline__ double uniform01(uint64_t w)
-{
-    return ((double)(w >> 12) + 0.5) * (1.0 / 4503599627370496.0);
-}
-
-// Random block of event e (0 = start, e >= 1 = e-th jump) of a trajectory.
-__device__ __forceinline__ U4 event_block(uint64_t seed, uint64_t traj_id, int64_t e)
-{
-    return philox4x64_10((uint64_t)e + 1u, traj_id, 0u, 0u, seed, 0u);
 }
 
 // --------------------------------------------------------- temperature ----

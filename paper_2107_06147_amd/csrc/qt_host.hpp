@@ -62,7 +62,7 @@ struct HostBatch {
     std::shared_ptr<const InitTable> init;
     int64_t vacuum_steps = 0;       // in-vacuum steps before the medium (once)
     qt_results zeroth{};            // device results of the zeroth trajectory
-    double r_min = 0;               // its smallest norm
+    int32_t* zdone = nullptr;       // its completion flag (device)
 };
 
 qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in,
@@ -106,12 +106,13 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
 // initial state.  Synchronises `s`.
 qt_status run_vacuum_phases(qt_context* ctx, const std::vector<HostBatch*>& hb, int prec,
                             hipStream_t s);
-// Runs the zeroth (no-jump) trajectory of every batch that asks for the
-// no-jump shortcut, all in one launch; sets each such batch's `zeroth`
-// (device results, held in *mem, which the caller frees stream-ordered after
-// its launch) and `r_min`.  Synchronises `s`.
-qt_status run_zeroth_trajectories(qt_context* ctx, const std::vector<HostBatch*>& hb, int prec,
-                                  hipStream_t s, void** mem);
+// For every batch that asks for the no-jump shortcut: a zeroth (no-jump)
+// trajectory group is appended to v/outs (stored in *zb) for the same launch,
+// and the batch is pointed at its results and completion flag (device
+// memory in *mem, which the caller frees stream-ordered after the launch).
+qt_status add_zeroth_groups(const std::vector<HostBatch*>& hb, std::vector<HostBatch>* zb,
+                            std::vector<const HostBatch*>* v, std::vector<qt_results>* outs,
+                            hipStream_t s, void** mem);
 
 // LPT order of (group, index) items: longest remaining work first.
 void build_items(const std::vector<const HostBatch*>& hb, std::vector<int32_t>* ig,

@@ -38,7 +38,7 @@ struct GroupDesc {
     TrajState* st;            // n_traj records (segmented runs), or null
     qt_results zeroth;        // no-jump trajectory's results (one entry, with
                               // psi), or all null: no shortcut
-    double     r_min;         // its smallest norm; thresholds below take it
+    int32_t*   zdone;         // set to 1 (release) once `zeroth` is complete
 };
 
 // Internal flag (above the public QT_FLAG_* bits): the group is the zeroth
@@ -67,6 +67,8 @@ fused_launcher fused_get(int prec, int N, int W);
 int fused_occupancy(int prec, int N, int W);
 
 hipError_t launch_queue_reset(int32_t* q, hipStream_t s);
+// zeroes n int32 values (a fill kernel, safe under graph capture)
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
 // complex values of the precision -> interleaved FP64 pairs
 hipError_t launch_widen(const void* src, int prec, double* dst, int64_t count, hipStream_t s);
 

@@ -317,7 +317,8 @@ __device__ __forceinline__ void write_results(const GroupDesc& g, int64_t idx, c
 #pragma unroll
         for (int bb = 0; bb < 6; ++bb) {
             double ov = 0.0, sv = 0.0;
-            if (status == QT_TRAJ_OK && c == QT_SINGLET && l == basis_l[bb] && nrm > 0.0) {
+            if ((status == QT_TRAJ_OK || status == QT_TRAJ_NOJUMP) && c == QT_SINGLET &&
+                l == basis_l[bb] && nrm > 0.0) {
                 const double dr_ = g.dr * x[2 * bb], di_ = g.dr * x[2 * bb + 1];
                 ov = (dr_ * dr_ + di_ * di_) / (g.dr * nrm);
                 sv = g.init_overlap[bb] != 0.0 ? ov / g.init_overlap[bb] : ov;
@@ -351,9 +352,12 @@ __device__ __forceinline__ void write_results(const GroupDesc& g, int64_t idx, c
 // Results of a trajectory that cannot jump: those of the batch's zeroth
 // trajectory (paper: Sec. "Summary of QTraj execution", step 4, r_0 < rMin),
 // with its own first threshold r and gap r_min - r (its gap to every norm of
-// that evolution, the smallest being at the smallest norm).
+// that evolution, the smallest being at the smallest norm).  The zeroth
+// trajectory runs as the first item of the same launch; a trajectory that
+// starts before it has finished is evolved instead, with the same results
+// (see the label at completion).
 template <int N, int W>
-__device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, double r)
+__device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, double r, double r_min)
 {
     const qt_results& z = g.zeroth;
     const qt_results& o = g.out;
@@ -371,7 +375,7 @@ __device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, dou
         if (o.n_jumps) o.n_jumps[idx] = 0;
         if (o.status) o.status[idx] = QT_TRAJ_NOJUMP;
         if (o.steps_done) o.steps_done[idx] = z.steps_done[0];
-        if (o.min_gap) o.min_gap[idx] = g.r_min - r;
+        if (o.min_gap) o.min_gap[idx] = r_min - r;
     }
     if (o.psi) {
         double* dst = o.psi + (size_t)idx * 2 * N;
@@ -392,6 +396,7 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
     __shared__ cx<R> wsum[W / 64];
     __shared__ double red[14 * (W / 64)];
     __shared__ int s_item;
+    __shared__ int s_zdone;
     // per-lane cache of the phase factors C_m between the two half-steps of a
     // step, kept when it still leaves room for two workgroups per CU
     constexpr bool kCache =
@@ -433,11 +438,24 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
             // the zeroth trajectory of a batch has threshold 0: it never jumps
             const U4 e0 = event_block(g.seed, traj_id, 0);
             r = uniform(g.flags & kFlagZeroth ? 0.0 : uniform01(e0.w[2]));
-            if (g.zeroth.norm != nullptr && r < g.r_min) {
-                // below every norm of the no-jump evolution: this trajectory
-                // is that evolution
-                take_zeroth<N, W>(g, idx, r);
-                continue;
+            if (g.zeroth.norm != nullptr) {
+                // has the batch's zeroth trajectory finished?  One decision
+                // for the whole workgroup, then each lane's own acquire
+                if (threadIdx.x == 0)
+                    s_zdone = __hip_atomic_load(g.zdone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                const int zd = __builtin_amdgcn_readfirstlane(s_zdone);
+                __syncthreads();
+                if (zd) {
+                    (void)__hip_atomic_load(g.zdone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    const double r_min = uniform(g.zeroth.min_gap[0]);
+                    if (r < r_min) {
+                        // below every norm of the no-jump evolution: this
+                        // trajectory is that evolution
+                        take_zeroth<N, W>(g, idx, r, r_min);
+                        continue;
+                    }
+                }
             }
             sfor<0, R1>([&](auto Rr) QT_INL {
                 const int ma = ln.ja + Rr * T, mb = ln.jb + Rr * T;
@@ -540,8 +558,20 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
         }
         const bool done = status != QT_TRAJ_OK || step >= g.n_steps;
         if (done) {
+            // in a batch with the no-jump shortcut, a trajectory that ran to
+            // the end without a jump evolved exactly as the zeroth one: its
+            // threshold lies below every norm of that evolution
+            if (g.zeroth.norm != nullptr && status == QT_TRAJ_OK && n_jumps == 0)
+                status = QT_TRAJ_NOJUMP;
             write_results<R, N, W>(g, idx, a, b, ln, red, l, c, n_jumps, status, step, norm,
                                    first_r, min_gap);
+            if (g.flags & kFlagZeroth) {
+                // publish: every lane's writes first, then the flag
+                __threadfence();
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(g.zdone, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         if (g.st) {
             // checkpoint (the final state too, so a job can return it)
@@ -564,6 +594,19 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
 }
 
 __global__ void queue_reset_kernel(int32_t* q) { *q = 0; }
+
+__global__ void zero_i32_kernel(int32_t* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    zero_i32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
 
 template <class R>
 __global__ void widen_kernel(const cx<R>* src, double* dst, int64_t count)

@@ -69,6 +69,8 @@ def test_shortcut_rejected_where_unavailable(ctx):
     cfg = dict(_cfg(n_traj=4), no_jump_shortcut=1)
     with pytest.raises(qt.QtError):
         qt.run(ctx, cfg, precision=F64, form=PLAIN)
+    with pytest.raises(qt.QtError):          # rMin is tested before rMax
+        qt.run(ctx, dict(cfg, r_max=0.9), precision=F64)
     with pytest.raises(qt.QtError):
         qt.Job(ctx, cfg, precision=F32, segment_steps=50)
     srv = qt.Server(ctx, precision=F32, segment_steps=50)
