@@ -83,8 +83,11 @@ enum { QT_FLAG_KINETIC_OFF = 1 };   /* kinetic factor := 1 (test special case) *
 
 /* Physics and grid (paper: table "Code parameters", groups Physics, Jump,
  * Grid).  Valid: N a power of two in [256, 8192]; L, dt, mass > 0;
- * alpha_s >= 0; kappa_hat >= 0; gamma_hat <= 0; deriv_type 0 or 1;
- * 0 < r_max <= 1; max_jumps < 0 means unlimited. */
+ * alpha_s >= 0; kappa_hat >= 0, or -1, -2, -3 for the central, lower and
+ * upper fit kappa_hat(T) = 1/(a x^{3/2} + b x + c x^{1/2} + d), x = T/T_c,
+ * T_c = 155 MeV (appendix "Munich potential"; 0 where the denominator is
+ * not positive); gamma_hat <= 0; deriv_type 0 or 1; 0 < r_max <= 1;
+ * max_jumps < 0 means unlimited. */
 typedef struct {
     int32_t N;
     double  L, dt, mass, alpha_s, kappa_hat, gamma_hat;

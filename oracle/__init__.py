@@ -106,6 +106,8 @@ def lib():
         L.qto_basis_state.restype = C.c_int
         L.qto_temperature.argtypes = [C.POINTER(_TTable), C.c_double]
         L.qto_temperature.restype = C.c_double
+        L.qto_kappa_hat.argtypes = [C.c_double, C.c_double]
+        L.qto_kappa_hat.restype = C.c_double
         _lib = L
     return _lib
 
@@ -237,3 +239,8 @@ def temperature(cfg, t):
     keep = []
     tt = _ttable(cfg, keep)
     return float(lib().qto_temperature(C.byref(tt), float(t)))
+
+
+def kappa_hat(kappa_hat_param, T):
+    """kappa_hat at temperature T (a constant, or one of the fits -1/-2/-3)."""
+    return float(lib().qto_kappa_hat(float(kappa_hat_param), float(T)))

@@ -200,12 +200,33 @@ static double kinetic_energy(const qto_physics* p, int32_t k)
     return pk * pk / p->mass;
 }
 
+/* kappa_hat at temperature T: the constant kappa_hat >= 0, or one of the
+ * fits to lattice data (appendix "Munich potential", the kappa_hat(T)
+ * parameterisation): kappa_hat = 1 / (a x^{3/2} + b x + c x^{1/2} + d),
+ * x = T / T_c, T_c = 155 MeV, for kappa_hat = -1 (central), -2 (lower),
+ * -3 (upper fit).  Below the fits' range, where the denominator is not
+ * positive (T below about 0.3 T_c), kappa_hat is taken as 0. */
+double qto_kappa_hat(double kappa_hat, double T)
+{
+    static const double fit[3][4] = {
+        { 0.00397, -0.08341, 0.98031, -0.51889 },   /* central */
+        { 0.00712, -0.14262, 1.55601, -0.80712 },   /* lower   */
+        { 0.00272, -0.05854, 0.71513, -0.38197 },   /* upper   */
+    };
+    if (kappa_hat >= 0.0) return kappa_hat;
+    int k = (int)(-kappa_hat) - 1;
+    double x = T / 0.155;
+    double sx = sqrt(x);
+    double den = fit[k][0] * x * sx + fit[k][1] * x + fit[k][2] * sx + fit[k][3];
+    return den > 0.0 ? 1.0 / den : 0.0;
+}
+
 /* V_eff = V_R + i V_I of the Munich potential plus the centrifugal term. */
 static void munich_potential(const qto_physics* p, double r, int32_t l, int32_t c,
                              double T, double* VR, double* VI)
 {
     double alpha = coulomb_alpha(p);
-    double kappa = p->kappa_hat * T * T * T;
+    double kappa = qto_kappa_hat(p->kappa_hat, T) * T * T * T;
     double gamma = p->gamma_hat * T * T * T;
     double centrifugal = (double)l * (double)(l + 1) / (p->mass * r * r);
     if (c == QTO_SINGLET) {
@@ -508,7 +529,8 @@ static int validate(const qto_physics* p, const qto_ttable* tt, const qto_init* 
     if (!p || !tt || !ini || !b) return -1;
     if (p->N < 4 || (p->N & (p->N - 1)) != 0) return -2;
     if (!(p->L > 0) || !(p->dt > 0) || !(p->mass > 0) || !(p->alpha_s >= 0)) return -3;
-    if (p->kappa_hat < 0 || p->gamma_hat > 0) return -4;
+    if (!(p->kappa_hat >= 0 || p->kappa_hat == -1.0 || p->kappa_hat == -2.0 || p->kappa_hat == -3.0)
+        || p->gamma_hat > 0) return -4;
     if (p->deriv_type != 0 && p->deriv_type != 1) return -5;
     if (!(p->r_max > 0) || p->r_max > 1) return -6;
     if (!tt->tau || !tt->T || tt->n < 2 || tt->max_steps < 0 || tt->vacuum_steps < 0) return -7;

@@ -36,7 +36,8 @@ typedef struct {
     double  dt;           /* time step, GeV^-1                                */
     double  mass;         /* heavy-quark mass M; kinetic energy p^2/M         */
     double  alpha_s;      /* strong coupling; alpha = C_F alpha_s             */
-    double  kappa_hat;    /* kappa = kappa_hat T^3                            */
+    double  kappa_hat;    /* kappa = kappa_hat T^3; -1/-2/-3: the central,
+                             lower, upper fit kappa_hat(T) (qto_kappa_hat)    */
     double  gamma_hat;    /* gamma = gamma_hat T^3                            */
     int32_t deriv_type;   /* 0: p^2/M, 1: 2(1-cos(p dr))/(M dr^2)             */
     int32_t do_jumps;     /* 0: H_eff evolution only                          */
@@ -116,6 +117,7 @@ void   qto_jump_rule(uint64_t seed, uint64_t traj_id, int64_t event,
 int    qto_basis_state(int32_t N, double L, double mass, double alpha_s,
                        int32_t n, int32_t l, double* u);
 double qto_temperature(const qto_ttable* tt, double t);
+double qto_kappa_hat(double kappa_hat, double T);
 
 #ifdef __cplusplus
 }

@@ -92,7 +92,8 @@ qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in, 
     if (!(p->L > 0) || !(p->dt > 0) || !(p->mass > 0))
         return fail(QT_EINVAL, "L, dt and mass must be > 0");
     if (!(p->alpha_s >= 0)) return fail(QT_EINVAL, "alpha_s must be >= 0");
-    if (!(p->kappa_hat >= 0)) return fail(QT_EINVAL, "kappa_hat must be >= 0");
+    if (!(p->kappa_hat >= 0 || p->kappa_hat == -1.0 || p->kappa_hat == -2.0 || p->kappa_hat == -3.0))
+        return fail(QT_EINVAL, "kappa_hat must be >= 0, or -1/-2/-3 for a fit");
     if (!(p->gamma_hat <= 0)) return fail(QT_EINVAL, "gamma_hat must be <= 0");
     if (p->deriv_type != 0 && p->deriv_type != 1) return fail(QT_EINVAL, "deriv_type must be 0 or 1");
     if (!(p->r_max > 0) || p->r_max > 1) return fail(QT_EINVAL, "r_max must be in (0, 1]");

@@ -69,6 +69,25 @@ __device__ __forceinline__ void qsincos(float x, float* s, float* c)
 }
 __device__ __forceinline__ void qsincos(double x, double* s, double* c) { sincos(x, s, c); }
 
+// kappa_hat at temperature T: the constant kappa_hat >= 0, or, for -1, -2,
+// -3, the central, lower and upper fits to lattice data of the appendix
+// "Munich potential", 1 / (a x^{3/2} + b x + c x^{1/2} + d) with
+// x = T / T_c, T_c = 155 MeV; 0 where that denominator is not positive
+// (below the fits' range).  Evaluated once per step, in FP64.
+__device__ __forceinline__ double kappa_hat_at(double kappa_hat, double T)
+{
+    if (kappa_hat >= 0.0) return kappa_hat;
+    const int k = (int)(-kappa_hat);
+    const double a = k == 1 ? 0.00397 : k == 2 ? 0.00712 : 0.00272;
+    const double b = k == 1 ? -0.08341 : k == 2 ? -0.14262 : -0.05854;
+    const double c = k == 1 ? 0.98031 : k == 2 ? 1.55601 : 0.71513;
+    const double d = k == 1 ? -0.51889 : k == 2 ? -0.80712 : -0.38197;
+    const double x = T / 0.155;
+    const double sx = sqrt(x);
+    const double den = a * x * sx + b * x + c * sx + d;
+    return den > 0.0 ? 1.0 / den : 0.0;
+}
+
 // Sum of K values over the workgroup, every lane receives all K sums.
 template <int W, int K>
 __device__ __forceinline__ void block_sum_vec(double* x, double* red)
@@ -488,11 +507,12 @@ __global__ __launch_bounds__(W) void fused_kernel(FusedArgs A)
             const double Tn = temperature_at(g.tau, g.Ttab, g.n_tab, t, cur);
             const double T3 = Tn * Tn * Tn;
             const double cc = (c == QT_SINGLET) ? 0.5 : 7.0 / 32.0;
-            const R zr = R(-0.5 * g.dt * cc * g.kappa_hat * T3);
+            const double kh = kappa_hat_at(g.kappa_hat, Tn);
+            const R zr = R(-0.5 * g.dt * cc * kh * T3);
             const R zi = R(-0.5 * g.dt * cc * g.gamma_hat * T3);
             const cx<R>* row = opaque(phase_row<R, N>(g, l, c));
             // FP64 always takes the library functions
-            const bool fast = !kRenorm || (fabs(-0.5 * g.dt * cc * g.kappa_hat * T3) * xmax <= 0.5 &&
+            const bool fast = !kRenorm || (fabs(-0.5 * g.dt * cc * kh * T3) * xmax <= 0.5 &&
                                            fabs(-0.5 * g.dt * cc * g.gamma_hat * T3) * xmax <= 0.78);
 
             cx<R> pw[Plan<N, W>::R1];
@@ -718,10 +738,10 @@ __global__ void plain_space_kernel(const GroupDesc* gp, double* psi, const TrajS
     double VR, VI;
     if (s.c == QT_SINGLET) {
         VR = -g.alpha / r + 0.5 * g.gamma_hat * T3 * r * r + cent;
-        VI = -0.5 * g.kappa_hat * T3 * r * r;
+        VI = -0.5 * kappa_hat_at(g.kappa_hat, T) * T3 * r * r;
     } else {
         VR = g.alpha / (8.0 * r) + (7.0 / 32.0) * g.gamma_hat * T3 * r * r + cent;
-        VI = -(7.0 / 32.0) * g.kappa_hat * T3 * r * r;
+        VI = -(7.0 / 32.0) * kappa_hat_at(g.kappa_hat, T) * T3 * r * r;
     }
     const double mag = exp(0.5 * g.dt * VI);
     double sn, cs;

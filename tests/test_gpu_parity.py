@@ -171,3 +171,20 @@ def test_unitary_evolution_keeps_the_norm(ctx, prec, tol):
     assert drift <= tol
     ref = oracle.run(cfg, n_traj=1)
     assert abs(ref["norm"][0] - 1.0) <= 1e-12
+
+
+# ------------------------------------------------ kappa_hat(T) lattice fits
+
+@pytest.mark.parametrize("fit", [-1.0, -2.0, -3.0])
+@pytest.mark.parametrize("prec,form", [(F64, FUSED), (F64, PLAIN), (F32, FUSED)])
+def test_kappa_fit_against_oracle(ctx, fit, prec, form):
+    """kappa_hat(T) from the central/lower/upper fit, along a cooling
+    Bjorken table, with jumps: every trajectory matches the oracle."""
+    tau, T = W.bjorken_table(0.5, 0.6, 0.25, 300)
+    cfg = W.base(N=512, L=20.0, dt=0.002, kappa_hat=fit, gamma_hat=-1.5, n_traj=10, seed=21,
+                 init_kind=W.INIT_GAUSSIAN, init_width=1.5, tau=tau, T=T,
+                 tau_start=float(tau[0]), T_final=0.25, max_steps=600)
+    ref = oracle.run(cfg, want_psi=True)
+    out = gpu_run(ctx, cfg, prec, form=form)
+    print("kappa fit", fit, prec, form, compare(ref, out, prec, label="kappa fit"),
+          "jumps", int(ref["n_jumps"].sum()))

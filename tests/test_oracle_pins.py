@@ -404,3 +404,37 @@ def test_vacuum_phase_then_medium_equals_stored_start(oracle_lib):
         assert np.array_equal(both[k], split[k]), k
     assert np.allclose(both["norm"], split["norm"], atol=1e-12)
     assert np.allclose(both["psi"], split["psi"], atol=1e-11)
+
+
+# ------------------------------------------------ kappa_hat(T) lattice fits
+
+def test_kappa_fits_ordered_and_decreasing(oracle_lib):
+    """The three fits are named lower, central and upper limit of the same
+    quantity, so over the plasma range T_c..4 T_c they are ordered
+    lower < central < upper, positive, and fall with T (appendix "Munich
+    potential", kappa = -2, -1, -3); a constant kappa_hat >= 0 passes
+    through unchanged."""
+    Tc = 0.155
+    prev = None
+    for x in np.linspace(1.0, 4.0, 31):
+        lo, ce, up = (oracle.kappa_hat(k, x * Tc) for k in (-2.0, -1.0, -3.0))
+        assert 0 < lo < ce < up
+        if prev is not None:
+            assert ce < prev
+        prev = ce
+    assert oracle.kappa_hat(2.5, 0.3) == 2.5
+    # far below the fits' range the width is switched off
+    assert oracle.kappa_hat(-1.0, 0.1 * Tc) == 0.0
+
+
+def test_kappa_fit_at_constant_temperature_is_a_constant_kappa(oracle_lib):
+    """At constant T the fit is one number: the run with kappa = -1 equals
+    the run with that constant kappa_hat, jumps included."""
+    T = 0.45
+    base = dict(N=256, L=20.0, dt=0.004, gamma_hat=-1.0, n_traj=12, seed=5,
+                init_kind=W.INIT_GAUSSIAN, init_width=2.0, **W.constant_T(T, 500))
+    fit = oracle.run(W.base(kappa_hat=-1.0, **base), want_psi=True)
+    const = oracle.run(W.base(kappa_hat=oracle.kappa_hat(-1.0, T), **base), want_psi=True)
+    for k in fit:
+        assert np.array_equal(fit[k], const[k]), k
+    assert fit["n_jumps"].sum() > 0
