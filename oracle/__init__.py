@@ -24,6 +24,7 @@ _lib = None
 SINGLET, OCTET = 0, 1
 INIT_COULOMB, INIT_GAUSSIAN, INIT_ARRAY = 0, 1, 2
 STATUS_OK, STATUS_RMAX, STATUS_MAXJUMPS, STATUS_NOJUMP = 0, 1, 2, 4
+POTENTIAL_MUNICH, POTENTIAL_KSU = 0, 1
 FLAG_KINETIC_OFF = 1
 BASIS = ("1S", "2S", "1P", "3S", "2P", "1D")
 
@@ -45,7 +46,7 @@ class _Physics(C.Structure):
                 ("kappa_hat", C.c_double), ("gamma_hat", C.c_double),
                 ("deriv_type", C.c_int32), ("do_jumps", C.c_int32),
                 ("max_jumps", C.c_int32), ("r_max", C.c_double),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("potential", C.c_int32), ("md_factor", C.c_double)]
 
 
 class _TTable(C.Structure):
@@ -108,6 +109,8 @@ def lib():
         L.qto_temperature.restype = C.c_double
         L.qto_kappa_hat.argtypes = [C.c_double, C.c_double]
         L.qto_kappa_hat.restype = C.c_double
+        L.qto_ksu_phi.argtypes = [C.c_double]
+        L.qto_ksu_phi.restype = C.c_double
         _lib = L
     return _lib
 
@@ -121,7 +124,8 @@ def _physics(cfg):
                     float(cfg["alpha_s"]), float(cfg["kappa_hat"]), float(cfg["gamma_hat"]),
                     int(cfg.get("deriv_type", 0)), int(cfg.get("do_jumps", 1)),
                     int(cfg.get("max_jumps", -1)), float(cfg.get("r_max", 1.0)),
-                    int(cfg.get("flags", 0)))
+                    int(cfg.get("flags", 0)), int(cfg.get("potential", 0)),
+                    float(cfg.get("md_factor", 1.0)))
 
 
 def _ttable(cfg, keep):
@@ -244,3 +248,8 @@ def temperature(cfg, t):
 def kappa_hat(kappa_hat_param, T):
     """kappa_hat at temperature T (a constant, or one of the fits -1/-2/-3)."""
     return float(lib().qto_kappa_hat(float(kappa_hat_param), float(T)))
+
+
+def ksu_phi(a):
+    """phi(a) of the imaginary part of the isotropic KSU potential."""
+    return float(lib().qto_ksu_phi(float(a)))

@@ -221,10 +221,99 @@ double qto_kappa_hat(double kappa_hat, double T)
     return den > 0.0 ? 1.0 / den : 0.0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Isotropic KSU potential (appendix "Isotropic KSU potential").            */
+/* ------------------------------------------------------------------------ */
+
+/* Ei(x) for x > 0: gamma + ln x + sum_k x^k / (k k!) (all terms positive). */
+static double ei_pos(double x)
+{
+    double term = 1.0, sum = 0.0;
+    for (int k = 1; k < 1000; ++k) {
+        term *= x / (double)k;
+        double add = term / (double)k;
+        sum += add;
+        if (add < 1e-17 * sum) break;
+    }
+    return 0.57721566490153286061 + log(x) + sum;
+}
+
+/* exp(x) E1(x), x > 0: the series E1 = -gamma - ln x - sum (-x)^k/(k k!) for
+ * x <= 1, the continued fraction E1 = exp(-x) / (x + 1 - 1/(x + 3 - 4/(x + 5
+ * - ...))) evaluated backwards from a deep truncation for x > 1. */
+static double exp_e1(double x)
+{
+    if (x <= 1.0) {
+        double term = 1.0, sum = 0.0;
+        for (int k = 1; k < 60; ++k) {
+            term *= -x / (double)k;
+            sum += term / (double)k;
+        }
+        return exp(x) * (-0.57721566490153286061 - log(x) - sum);
+    }
+    double f = 0.0;
+    for (int k = 400; k >= 1; --k) f = (double)k * (double)k / (x + 2.0 * k + 1.0 - f);
+    return 1.0 / (x + 1.0 - f);
+}
+
+/* phi(a) = 2 int_0^inf dz z/(z^2+1)^2 [1 - sin(z a)/(z a)]
+ *        = 1 - (2/a) I(a),  I(a) = int_0^inf sin(a z)/(1+z^2)^2 dz
+ *        = [(a+1) e^{-a} Ei(a) + (a-1) e^{a} Ei(-a)] / 4,
+ * the closed form from the sine integral of 1/(z^2+b^2) in terms of Ei,
+ * differentiated in b at b = 1.  For large a the asymptotic series
+ * 1 - 2/a^2 - 8/a^4 - 144/a^6 - 5760/a^8 - 403200/a^10 (from the
+ * derivatives of 1/(1+z^2)^2 at 0). */
+double qto_ksu_phi(double a)
+{
+    if (a <= 0.0) return 0.0;
+    if (a >= 100.0) {
+        double q = 1.0 / (a * a);
+        return 1.0 - q * (2.0 + q * (8.0 + q * (144.0 + q * (5760.0 + q * 403200.0))));
+    }
+    double ep = exp(-a) * ei_pos(a);          /* e^{-a} Ei(a)  */
+    double em = -exp_e1(a);                   /* e^{a} Ei(-a)  */
+    double I = 0.25 * ((a + 1.0) * ep + (a - 1.0) * em);
+    return 1.0 - 2.0 * I / a;
+}
+
+/* Constants of the KSU potential: effective coupling, string tension,
+ * string-breaking distance 1.25 fm, alpha_s(5 GeV) = 0.2034 run at one loop
+ * with N_F = 3 light flavours (b0 = 11 - 2 N_F/3) to the scale 2 pi T. */
+static const double KSU_A = 0.409, KSU_SIGMA = 0.21, KSU_RSB = 1.25 / 0.1973269804;
+static const double KSU_AS0 = 0.2034, KSU_MU0 = 5.0, KSU_NF = 3.0, KSU_NC = 3.0;
+
+/* alpha_s(2 pi T); <= 0 at and below the one-loop pole (no medium there). */
+static double ksu_alpha_s(double T)
+{
+    if (!(T > 0.0)) return 0.0;
+    double inv = 1.0 / KSU_AS0 + (11.0 - 2.0 * KSU_NF / 3.0) / (2.0 * PI) * log(2.0 * PI * T / KSU_MU0);
+    return inv > 0.0 ? 1.0 / inv : 0.0;
+}
+
+static void ksu_potential(const qto_physics* p, double r, int32_t l, double T, double* VR, double* VI)
+{
+    double as = ksu_alpha_s(T);
+    double mD = 0.0;
+    if (as > 0.0)
+        mD = p->md_factor * T * sqrt(KSU_NC * (1.0 + KSU_NF / 6.0) * PI * (4.0 / 3.0) * as);
+    double x = mD * r;
+    /* (1 - e^{-x})/x, 1 at x = 0 */
+    double q = x > 0.0 ? -expm1(-x) / x : 1.0;
+    double e = exp(-x);
+    double kms = -KSU_A / r * (1.0 + x) * e + 2.0 * KSU_SIGMA * r * q - KSU_SIGMA * r * e;
+    double vsb = -KSU_A / KSU_RSB + KSU_SIGMA * KSU_RSB;
+    *VR = (kms <= vsb ? kms : vsb) + (double)l * (double)(l + 1) / (p->mass * r * r);
+    *VI = -as * (4.0 / 3.0) * T * qto_ksu_phi(x);
+}
+
 /* V_eff = V_R + i V_I of the Munich potential plus the centrifugal term. */
 static void munich_potential(const qto_physics* p, double r, int32_t l, int32_t c,
                              double T, double* VR, double* VI)
 {
+    if (p->potential == QTO_POTENTIAL_KSU) {
+        ksu_potential(p, r, l, T, VR, VI);
+        return;
+    }
     double alpha = coulomb_alpha(p);
     double kappa = qto_kappa_hat(p->kappa_hat, T) * T * T * T;
     double gamma = p->gamma_hat * T * T * T;
@@ -532,6 +621,10 @@ static int validate(const qto_physics* p, const qto_ttable* tt, const qto_init* 
     if (!(p->kappa_hat >= 0 || p->kappa_hat == -1.0 || p->kappa_hat == -2.0 || p->kappa_hat == -3.0)
         || p->gamma_hat > 0) return -4;
     if (p->deriv_type != 0 && p->deriv_type != 1) return -5;
+    if (p->potential != QTO_POTENTIAL_MUNICH && p->potential != QTO_POTENTIAL_KSU) return -5;
+    /* the KSU potential is a singlet potential without jumps */
+    if (p->potential == QTO_POTENTIAL_KSU &&
+        (p->do_jumps || ini->color != QTO_SINGLET || !(p->md_factor > 0))) return -5;
     if (!(p->r_max > 0) || p->r_max > 1) return -6;
     if (!tt->tau || !tt->T || tt->n < 2 || tt->max_steps < 0 || tt->vacuum_steps < 0) return -7;
     for (int32_t k = 0; k + 1 < tt->n; ++k) if (!(tt->tau[k + 1] > tt->tau[k])) return -7;

@@ -29,6 +29,7 @@ enum { QTO_INIT_COULOMB = 0, QTO_INIT_GAUSSIAN = 1, QTO_INIT_ARRAY = 2 };
 enum { QTO_STATUS_OK = 0, QTO_STATUS_RMAX = 1, QTO_STATUS_MAXJUMPS = 2,
        QTO_STATUS_NOJUMP = 4 };   /* 4: results taken from the no-jump trajectory */
 enum { QTO_FLAG_KINETIC_OFF = 1 };   /* test flag: kinetic factor := 1 */
+enum { QTO_POTENTIAL_MUNICH = 0, QTO_POTENTIAL_KSU = 1 };
 
 typedef struct {
     int32_t N;            /* grid points (N-1 unknowns)                      */
@@ -44,6 +45,10 @@ typedef struct {
     int32_t max_jumps;    /* < 0: unlimited                                   */
     double  r_max;        /* first threshold above r_max: zero overlaps       */
     int32_t flags;        /* QTO_FLAG_*                                       */
+    int32_t potential;    /* QTO_POTENTIAL_*: Munich (appendix "Munich
+                             potential") or isotropic KSU (appendix
+                             "Isotropic KSU potential"; singlet, no jumps)    */
+    double  md_factor;    /* KSU: the Debye-mass factor F_mD                  */
 } qto_physics;
 
 typedef struct {
@@ -118,6 +123,7 @@ int    qto_basis_state(int32_t N, double L, double mass, double alpha_s,
                        int32_t n, int32_t l, double* u);
 double qto_temperature(const qto_ttable* tt, double t);
 double qto_kappa_hat(double kappa_hat, double T);
+double qto_ksu_phi(double a);
 
 #ifdef __cplusplus
 }

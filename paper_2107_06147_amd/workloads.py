@@ -13,7 +13,7 @@ them.
 
 Every config is a plain dict with the keys
   N, L, dt, mass, alpha_s, kappa_hat, gamma_hat, deriv_type, do_jumps,
-  max_jumps, r_max, flags,
+  max_jumps, r_max, flags, potential, md_factor,
   tau, T, tau_start, T_final, max_steps, vacuum_steps,
   init_kind, init_n, init_l, init_color, init_width,
   n_traj, seed, traj_id0, traj_id_stride, no_jump_shortcut
@@ -28,12 +28,14 @@ MASS_B = 4.65                 # bottom-quark mass, GeV
 ALPHA_S = 0.3
 
 SINGLET, OCTET = 0, 1
+POTENTIAL_MUNICH, POTENTIAL_KSU = 0, 1
 INIT_COULOMB, INIT_GAUSSIAN, INIT_ARRAY = 0, 1, 2
 
 
 def base(**kw):
     cfg = dict(N=512, L=40.0, dt=0.001, mass=MASS_B, alpha_s=ALPHA_S, kappa_hat=4.0,
                gamma_hat=0.0, deriv_type=0, do_jumps=1, max_jumps=-1, r_max=1.0, flags=0,
+               potential=0, md_factor=1.0,
                tau=np.array([0.0, 1.0e9]), T=np.array([0.4, 0.4]), tau_start=0.0,
                T_final=0.0, max_steps=1000, vacuum_steps=0,
                init_kind=INIT_COULOMB, init_n=1, init_l=0, init_color=SINGLET, init_width=0.0,

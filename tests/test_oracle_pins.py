@@ -438,3 +438,74 @@ def test_kappa_fit_at_constant_temperature_is_a_constant_kappa(oracle_lib):
     for k in fit:
         assert np.array_equal(fit[k], const[k]), k
     assert fit["n_jumps"].sum() > 0
+
+
+# -------------------------------------------------- isotropic KSU potential
+
+KSU_A, KSU_SIGMA, KSU_RSB = 0.409, 0.21, 1.25 / W.HBARC
+
+
+def test_ksu_phi_against_quadrature(oracle_lib):
+    """phi(a) = 2 int_0^inf dz z/(z^2+1)^2 [1 - sin(za)/(za)] (appendix
+    "Isotropic KSU potential"), against high-precision oscillatory
+    quadrature of that integral; phi(0) = 0 and phi -> 1."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 30
+    for a in (0.1, 0.5, 1.0, 2.0, 5.0, 10.0, 30.0, 64.0, 99.0, 150.0):
+        I = mpmath.quadosc(lambda z: mpmath.sin(a * z) / (1 + z * z) ** 2, [0, mpmath.inf], omega=a)
+        assert abs(oracle.ksu_phi(a) - float(1 - 2 * I / a)) < 1e-13, a
+    assert oracle.ksu_phi(0.0) == 0.0
+    assert 0 < oracle.ksu_phi(1e-3) < 1e-4 and abs(oracle.ksu_phi(1e4) - 1.0) < 1e-7
+
+
+def test_ksu_at_zero_temperature_is_cornell_with_string_breaking(oracle_lib):
+    """T = 0: no screening and no width; V = -a/r + sigma r up to the string
+    breaking distance 1.25 fm, constant beyond.  The lowest discrete
+    eigenstate of that H evolves by its phase only."""
+    N, L, dt, steps = 512, 20.0, 0.001, 1500
+    M = W.MASS_B
+    j = np.arange(1, N)
+    r = j * L / N
+    S = np.sqrt(2.0 / N) * np.sin(np.pi * np.outer(j, j) / N)
+    V = np.where(r <= KSU_RSB, -KSU_A / r + KSU_SIGMA * r, -KSU_A / KSU_RSB + KSU_SIGMA * KSU_RSB)
+    H = S @ np.diag((np.pi * j / L) ** 2 / M) @ S + np.diag(V)
+    E, U = np.linalg.eigh(H)
+    dr = L / N
+    u0 = np.zeros(N, complex)
+    u0[1:] = U[:, 0] * np.sign(U[np.argmax(np.abs(U[:, 0])), 0])
+    u0 /= np.sqrt(dr * np.sum(np.abs(u0) ** 2))
+    cfg = W.base(N=N, L=L, dt=dt, potential=W.POTENTIAL_KSU, do_jumps=0, kappa_hat=0.0,
+                 init_kind=W.INIT_ARRAY, n_traj=1, **W.constant_T(0.0, steps))
+    cfg["u0"] = u0
+    out = oracle.run(cfg, want_psi=True)
+    assert abs(out["norm"][0] - 1.0) < 1e-12
+    c = dr * np.vdot(u0, out["psi"][0])
+    assert abs(abs(c) ** 2 - 1.0) < 1e-6
+    assert abs(np.angle(c * np.exp(1j * E[0] * dt * steps))) < 1e-5 * abs(E[0]) * dt * steps + 1e-6
+
+
+def test_ksu_width_decay_closed_form(oracle_lib):
+    """Kinetic factor switched off and T constant: the state only decays,
+    norm_n = dr sum_j |u_j|^2 exp(2 n dt V_I(r_j)) with
+    V_I = -alpha_s(2 pi T) C_F T phi(m_D r) (phi from quadrature; the
+    one-loop coupling from alpha_s(5 GeV) = 0.2034 with 3 flavours and the
+    Debye mass of the appendix restated here)."""
+    from scipy import integrate
+    N, L, dt, steps, T = 256, 20.0, 0.002, 400, 0.35
+    out = oracle.run(W.base(N=N, L=L, dt=dt, potential=W.POTENTIAL_KSU, do_jumps=0,
+                            kappa_hat=0.0, flags=oracle.FLAG_KINETIC_OFF,
+                            init_kind=W.INIT_GAUSSIAN, init_width=2.0, n_traj=1,
+                            **W.constant_T(T, steps)), want_psi=True)
+    inv = 1 / 0.2034 + (11 - 2.0) / (2 * np.pi) * np.log(2 * np.pi * T / 5.0)
+    a_s = 1 / inv
+    mD = T * np.sqrt(3 * (1 + 3 / 6.0) * np.pi * 4 / 3 * a_s)
+    dr = L / N
+    r = np.arange(1, N) * dr
+    # the sine-weighted (Fourier) quadrature of the defining integral
+    phi = np.array([1 - 2 * integrate.quad(lambda z: 1 / (1 + z * z) ** 2, 0, np.inf,
+                                           weight="sin", wvar=x)[0] / x for x in mD * r])
+    VI = -a_s * 4 / 3 * T * phi
+    u = r ** 1 * np.exp(-r ** 2 / (2 * 4.0))
+    u /= np.sqrt(dr * np.sum(u ** 2))
+    expect = dr * np.sum(u ** 2 * np.exp(2 * steps * dt * VI))   # |exp(dt V_I / 2)|^2 twice a step
+    assert abs(out["norm"][0] - expect) < 1e-10
