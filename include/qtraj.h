@@ -80,6 +80,15 @@ typedef enum { QT_SINGLET = 0, QT_OCTET = 1 } qt_color;
 typedef enum { QT_TRAJ_OK = 0, QT_TRAJ_RMAX = 1, QT_TRAJ_MAXJUMPS = 2, QT_TRAJ_LMAX = 3,
                QT_TRAJ_NOJUMP = 4 } qt_traj_status;
 enum { QT_FLAG_KINETIC_OFF = 1 };   /* kinetic factor := 1 (test special case) */
+/* MUNICH: appendix "Munich potential" (singlet/octet, jumps).  KSU: appendix
+ * "Isotropic KSU potential": screened Karsch-Mehr-Satz real part with string
+ * breaking at 1.25 fm (a = 0.409, sigma = 0.21 GeV^2), imaginary part
+ * -alpha_s C_F T phi(m_D r); alpha_s(2 pi T) at one loop from
+ * alpha_s(5 GeV) = 0.2034 with 3 light flavours; Debye mass
+ * m_D = md_factor T sqrt(N_c (1 + N_F/6) pi (4/3) alpha_s).  Singlet only,
+ * no jumps (do_jumps = 0); no medium where T = 0 or below the coupling's
+ * one-loop pole. */
+typedef enum { QT_POTENTIAL_MUNICH = 0, QT_POTENTIAL_KSU = 1 } qt_potential;
 
 /* Physics and grid (paper: table "Code parameters", groups Physics, Jump,
  * Grid).  Valid: N a power of two in [256, 8192]; L, dt, mass > 0;
@@ -94,6 +103,8 @@ typedef struct {
     int32_t deriv_type, do_jumps, max_jumps;
     double  r_max;
     int32_t flags;
+    int32_t potential;     /* qt_potential */
+    double  md_factor;     /* KSU: > 0 */
 } qt_physics;
 
 /* Temperature table (paper: Temperature parameters).  Host pointers, read

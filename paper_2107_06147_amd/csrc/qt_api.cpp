@@ -129,6 +129,14 @@ qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in, 
     if (b->form == QT_FORM_PLAIN && b->precision != QT_FP64)
         return fail(QT_EINVAL, "the plain form is FP64 only");
     if (tt->vacuum_steps < 0) return fail(QT_EINVAL, "vacuum_steps must be >= 0");
+    if (p->potential != QT_POTENTIAL_MUNICH && p->potential != QT_POTENTIAL_KSU)
+        return fail(QT_EINVAL, "unknown potential %d", p->potential);
+    if (p->potential == QT_POTENTIAL_KSU) {
+        if (p->do_jumps) return fail(QT_EINVAL, "the KSU potential runs without jumps");
+        if (in->color != QT_SINGLET) return fail(QT_EINVAL, "the KSU potential is a singlet potential");
+        if (!(p->md_factor > 0) || !std::isfinite(p->md_factor))
+            return fail(QT_EINVAL, "md_factor must be > 0");
+    }
     if (b->no_jump_shortcut != 0 && b->no_jump_shortcut != 1)
         return fail(QT_EINVAL, "no_jump_shortcut must be 0 or 1");
     if (b->no_jump_shortcut && b->form != QT_FORM_FUSED)
@@ -330,30 +338,140 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
         return QT_OK;
     }
     const bool f32 = prec == QT_FP32_BULK;
-    // FFT twiddles exp(-2 pi i m/N); DST pre-processing weights
-    // ((s + 1/2)/2, (s - 1/2)/2) with s = sin(pi m/N)
-    std::vector<double> tw(2 * (size_t)N), sn(2 * (size_t)N);
-    for (int m = 0; m < N; ++m) {
-        tw[2 * m] = std::cos(2.0 * kPi * m / N);
-        tw[2 * m + 1] = -std::sin(2.0 * kPi * m / N);
-        const double s = std::sin(kPi * m / N);
-        sn[2 * m] = 0.5 * (s + 0.5);
-        sn[2 * m + 1] = 0.5 * (s - 0.5);
-    }
+    // FFT twiddles exp(-2 pi i m/n) and DST-I pre-processing weights
+    // ((s + 1/2)/2, (s - 1/2)/2), s = sin(pi m/n), of a transform of length n
+    auto fill = [](int n, double* tw, double* sn) {
+        for (int m = 0; m < n; ++m) {
+            tw[2 * m] = std::cos(2.0 * kPi * m / n);
+            tw[2 * m + 1] = -std::sin(2.0 * kPi * m / n);
+            const double s = std::sin(kPi * m / n);
+            sn[2 * m] = 0.5 * (s + 0.5);
+            sn[2 * m + 1] = 0.5 * (s - 0.5);
+        }
+    };
     qt_context::Tables t;
-    const size_t eb = f32 ? 4 : 8;
-    QT_HIP(hipMalloc(&t.tw, 2 * N * eb));
-    QT_HIP(hipMalloc(&t.prew, 2 * N * eb));
     if (f32) {
-        std::vector<float> a(tw.begin(), tw.end()), b(sn.begin(), sn.end());
-        QT_HIP(hipMemcpy(t.tw, a.data(), a.size() * 4, hipMemcpyHostToDevice));
-        QT_HIP(hipMemcpy(t.prew, b.data(), b.size() * 4, hipMemcpyHostToDevice));
+        // the FP32 sine transform (split form, qt_dst32.hpp), one block:
+        // FP32 [FFT twiddles of length M = N/2 | exp(-i pi j/N), j < M],
+        // FP64 [FFT twiddles, DST-I weights of length M | the same of length N]
+        const int M = N / 2;
+        std::vector<float> f(4 * (size_t)M);
+        for (int m = 0; m < M; ++m) {
+            f[2 * m] = (float)std::cos(2.0 * kPi * m / M);
+            f[2 * m + 1] = (float)-std::sin(2.0 * kPi * m / M);
+            f[2 * (M + m)] = (float)std::cos(kPi * m / N);
+            f[2 * (M + m) + 1] = (float)-std::sin(kPi * m / N);
+        }
+        std::vector<double> d(4 * (size_t)M + 4 * (size_t)N);
+        fill(M, &d[0], &d[2 * (size_t)M]);
+        fill(N, &d[4 * (size_t)M], &d[4 * (size_t)M + 2 * (size_t)N]);
+        QT_HIP(hipMalloc(&t.tw, f.size() * 4 + d.size() * 8));
+        QT_HIP(hipMemcpy(t.tw, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+        QT_HIP(hipMemcpy(static_cast<char*>(t.tw) + f.size() * 4, d.data(), d.size() * 8,
+                         hipMemcpyHostToDevice));
+        t.prew = nullptr;
     } else {
+        std::vector<double> tw(2 * (size_t)N), sn(2 * (size_t)N);
+        fill(N, tw.data(), sn.data());
+        QT_HIP(hipMalloc(&t.tw, 2 * N * 8));
+        QT_HIP(hipMalloc(&t.prew, 2 * N * 8));
         QT_HIP(hipMemcpy(t.tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
         QT_HIP(hipMemcpy(t.prew, sn.data(), sn.size() * 8, hipMemcpyHostToDevice));
     }
     ctx->tables[key] = t;
     *out = t;
+    return QT_OK;
+}
+
+// ------------------------------------------------ KSU phi(r-hat) table ---
+//
+// phi(a) = 2 int_0^inf dz z/(z^2+1)^2 [1 - sin(z a)/(z a)] of the KSU
+// potential's imaginary part (appendix "Isotropic KSU potential").  With
+// I(a) = int_0^inf sin(a z)/(1+z^2)^2 dz, phi = 1 - 2 I/a, and from the sine
+// integral of 1/(z^2+b^2) in terms of the exponential integral,
+// differentiated in b at b = 1:
+//   I(a)  = [(a+1) e^{-a} Ei(a) + (a-1) e^{a} Ei(-a)] / 4,
+//   I'(a) = [2 - a e^{-a} Ei(a) + a e^{a} Ei(-a)] / 4,
+//   phi'(a) = 2 I/a^2 - 2 I'/a.
+// Table: (phi, phi') at a = k/8192, k = 0..4096, then at a = 1/2 + k/256,
+// k = 0..16256, for cubic Hermite interpolation on the device.
+
+// e^{-a} Ei(a), a > 0 (power series of Ei, positive terms)
+static double scaled_ei(double a)
+{
+    double t = 1.0, s = 0.0;
+    for (int k = 1; k < 2000; ++k) {
+        t *= a / k;
+        const double d = t / k;
+        s += d;
+        if (d <= 1e-18 * s) break;
+    }
+    return std::exp(-a) * (0.5772156649015328606 + std::log(a) + s);
+}
+
+// e^{a} E1(a) = -e^{a} Ei(-a), a > 0: series below 1, continued fraction
+// (modified Lentz) above
+static double scaled_e1(double a)
+{
+    if (a < 1.0) {
+        double t = 1.0, s = 0.0;        // sum_k (-a)^k / (k k!)
+        for (int k = 1; k < 40; ++k) {
+            t *= -a / k;
+            s += t / k;
+        }
+        return std::exp(a) * (-0.5772156649015328606 - std::log(a) - s);
+    }
+    const double tiny = 1e-300;
+    double b = a + 1.0, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int i = 1; i < 10000; ++i) {
+        const double an = -(double)i * i;
+        b += 2.0;
+        d = 1.0 / (an * d + b);
+        c = b + an / c;
+        const double del = c * d;
+        h *= del;
+        if (std::fabs(del - 1.0) < 1e-16) break;
+    }
+    return h;
+}
+
+static void ksu_phi_and_slope(double a, double* phi, double* dphi)
+{
+    if (a <= 0.0) {
+        *phi = 0.0;
+        *dphi = 0.0;
+        return;
+    }
+    const double ep = scaled_ei(a), em = -scaled_e1(a);
+    const double I = 0.25 * ((a + 1.0) * ep + (a - 1.0) * em);
+    const double Ip = 0.25 * (2.0 - a * ep + a * em);
+    *phi = 1.0 - 2.0 * I / a;
+    *dphi = 2.0 * I / (a * a) - 2.0 * Ip / a;
+}
+
+qt_status ensure_ksu_table(qt_context* ctx, int prec, const void** out)
+{
+    auto it = ctx->ksu_phi.find(prec);
+    if (it != ctx->ksu_phi.end()) {
+        *out = it->second;
+        return QT_OK;
+    }
+    const int nf = 4097, nc = 16257;
+    std::vector<double> v(2 * (size_t)(nf + nc));
+    for (int k = 0; k < nf; ++k) ksu_phi_and_slope(k / 8192.0, &v[2 * k], &v[2 * k + 1]);
+    for (int k = 0; k < nc; ++k)
+        ksu_phi_and_slope(0.5 + k / 256.0, &v[2 * (nf + k)], &v[2 * (nf + k) + 1]);
+    void* d = nullptr;
+    if (prec == QT_FP32_BULK) {
+        std::vector<float> f(v.begin(), v.end());
+        QT_HIP(hipMalloc(&d, f.size() * 4));
+        QT_HIP(hipMemcpy(d, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    } else {
+        QT_HIP(hipMalloc(&d, v.size() * 8));
+        QT_HIP(hipMemcpy(d, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+    }
+    ctx->ksu_phi[prec] = d;
+    *out = d;
     return QT_OK;
 }
 
@@ -465,12 +583,17 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         o[g].Tn = off;
         if (with_Tn) off = align_up(off + (size_t)std::max<int64_t>(h.n_steps, 1) * 8);
     }
-    std::vector<const void*> phase(ng, nullptr);
+    std::vector<const void*> phase(ng, nullptr), ksu(ng, nullptr);
     if (!with_Tn)
         for (size_t g = 0; g < ng; ++g) {
             qt_status st = ensure_phase(ctx, *hb[g], prec, &phase[g]);
             if (st != QT_OK) return st;
         }
+    for (size_t g = 0; g < ng; ++g) {
+        if (hb[g]->phys.potential != QT_POTENTIAL_KSU) continue;
+        qt_status st = ensure_ksu_table(ctx, prec, &ksu[g]);
+        if (st != QT_OK) return st;
+    }
     dg->bytes = off;
     if (async_alloc) {
         QT_HIP(hipMallocAsync(&dg->mem, off, s));
@@ -507,18 +630,27 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         d.st = nullptr;
         d.zeroth = h.zeroth;
         d.zdone = h.zdone;
+        d.potential = h.phys.potential;
+        d.md_factor = h.phys.md_factor;
+        d.ksu_phi = ksu[g];
         dg->host[g] = d;
         std::memcpy(&blob[o[g].tau], h.tau.data(), h.tau.size() * 8);
         std::memcpy(&blob[o[g].T], h.T.data(), h.T.size() * 8);
         if (o[g].own_kin && f32) {
-            // double-float kinetic factor per momentum: hi rounded, lo the rest
-            float* k = reinterpret_cast<float*>(&blob[o[g].kin]);
-            for (int m = 0; m < N; ++m) {
-                for (int c = 0; c < 2; ++c) {
-                    const double x = (*h.kin)[2 * m + c];
-                    k[4 * m + c] = (float)x;
-                    k[4 * m + 2 + c] = (float)(x - (double)k[4 * m + c]);
-                }
+            // in the output order of the FP32 sine transform: entry n < N/2
+            // is the factor of the odd output that the half-length cosine
+            // transform leaves in slot n, k = 4n + 1 (times 1/2) below N/4
+            // and k = 2N - 4n - 1 (times -1/2) above; entry N/2 + q that of
+            // the even output k = 2q
+            double* k = reinterpret_cast<double*>(&blob[o[g].kin]);
+            const int M = N / 2;
+            for (int n = 0; n < M; ++n) {
+                const int ko = n < M / 2 ? 4 * n + 1 : 2 * N - 4 * n - 1;
+                const double so = n < M / 2 ? 0.5 : -0.5;
+                k[2 * n] = so * (*h.kin)[2 * ko];
+                k[2 * n + 1] = so * (*h.kin)[2 * ko + 1];
+                k[2 * (M + n)] = (*h.kin)[4 * n];
+                k[2 * (M + n) + 1] = (*h.kin)[4 * n + 1];
             }
         } else if (o[g].own_kin) {
             std::memcpy(&blob[o[g].kin], h.kin->data(), 2 * (size_t)N * 8);
@@ -645,6 +777,7 @@ qt_status qt_context_destroy(qt_context* ctx)
         hipFree(kv.second.prew);
     }
     for (auto& kv : ctx->phase) hipFree(kv.second);
+    for (auto& kv : ctx->ksu_phi) hipFree(kv.second);
     for (hipStream_t s : ctx->aux) hipStreamDestroy(s);
     hipEventDestroy(ctx->ev0);
     hipEventDestroy(ctx->ev1);
@@ -674,13 +807,33 @@ qt_status qt_plan(qt_context* ctx, int32_t N, int32_t precision, int32_t tune,
 
 namespace qt {
 
+qt_status pick_launcher(qt_context* ctx, int prec, int N, int potential, int* W,
+                        fused_launcher* launch, int* slots_per_cu)
+{
+    if (potential == QT_POTENTIAL_KSU) {
+        if (!fused_ksu_variant(prec, N, W, launch, slots_per_cu) || *slots_per_cu <= 0)
+            return fail(QT_EDEVICE, "no KSU kernel for N=%d", N);
+        return QT_OK;
+    }
+    qt_context::Variant v;
+    qt_status st = choose_variant(ctx, prec, N, &v);
+    if (st != QT_OK) return st;
+    *W = v.W;
+    *launch = fused_get(prec, N, v.W);
+    *slots_per_cu = v.slots_per_cu;
+    return *launch ? QT_OK : fail(QT_EDEVICE, "no kernel for N=%d", N);
+}
+
 qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb,
                            const std::vector<qt_results>& outs, int prec, hipStream_t s)
 {
-    // one persistent launch per grid size N (kernels are specialised per N)
+    // one persistent launch per (grid size N, potential): the kernels are
+    // specialised on both; a class is keyed 2 N + potential
     std::vector<int> Ns;
-    for (const HostBatch* h : hb)
-        if (std::find(Ns.begin(), Ns.end(), h->phys.N) == Ns.end()) Ns.push_back(h->phys.N);
+    for (const HostBatch* h : hb) {
+        const int key = 2 * h->phys.N + h->phys.potential;
+        if (std::find(Ns.begin(), Ns.end(), key) == Ns.end()) Ns.push_back(key);
+    }
     DeviceGroups dg;
     qt_status st = upload_groups(ctx, hb, prec, outs, false, s, true, &dg);
     if (st != QT_OK) return st;
@@ -700,10 +853,10 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
     std::vector<int32_t> ig2;
     std::vector<int64_t> ii2;
     std::vector<size_t> start, count;
-    for (int N : Ns) {
+    for (int key : Ns) {
         start.push_back(ig2.size());
         for (size_t k = 0; k < n_items; ++k)
-            if (hb[ig[k]]->phys.N == N) {
+            if (2 * hb[ig[k]]->phys.N + hb[ig[k]]->phys.potential == key) {
                 ig2.push_back(ig[k]);
                 ii2.push_back(ii[k]);
             }
@@ -718,9 +871,10 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
     int64_t launches = 0;
     for (size_t c = 0; c < Ns.size(); ++c) {
         if (count[c] == 0) continue;
-        const int N = Ns[c];
-        qt_context::Variant v;
-        if ((st = choose_variant(ctx, prec, N, &v)) != QT_OK) return st;
+        const int N = Ns[c] / 2, pot = Ns[c] % 2;
+        int W = 0, slots = 0;
+        fused_launcher launch = nullptr;
+        if ((st = pick_launcher(ctx, prec, N, pot, &W, &launch, &slots)) != QT_OK) return st;
         qt_context::Tables t;
         if ((st = ensure_tables(ctx, prec, N, &t)) != QT_OK) return st;
         FusedArgs a;
@@ -732,9 +886,9 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
         a.tw = t.tw;
         a.prew = t.prew;
         a.seg_steps = 0;
-        const int grid = (int)std::min<int64_t>((int64_t)count[c], (int64_t)ctx->n_cu * v.slots_per_cu);
+        const int grid = (int)std::min<int64_t>((int64_t)count[c], (int64_t)ctx->n_cu * slots);
         QT_HIP(launch_queue_reset(a.queue, s));
-        QT_HIP(fused_get(prec, N, v.W)(a, grid, s));
+        QT_HIP(launch(a, grid, s));
         launches += 2;
     }
     QT_HIP(hipEventRecord(ctx->ev1, s));

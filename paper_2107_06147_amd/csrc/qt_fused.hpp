@@ -1,0 +1,763 @@
+// qt_fused.hpp -- the fused persistent kernel of the quantum-trajectory
+// solver and its per-step building blocks (half-step factors of the Munich
+// and the isotropic KSU potentials, the FP32 elementary functions, the
+// shortcut copy, the results).  Instantiated per (precision, N, W,
+// potential) by qt_kernels.hip (Munich) and qt_kernels_ksu.hip (KSU).
+#pragma once
+#include "qt_device.hpp"
+#include "qt_dst32.hpp"
+#include "qt_internal.h"
+
+namespace qt {
+
+// FP32 exp(x) - 1 without branches: the Taylor series to x^8 on |x| < 1/2
+// (remainder < 2e-8 relative), exp2 - 1 elsewhere (there |result| > 0.39 and
+// the absolute error of exp2 is a relative error ~1e-7).
+__device__ __forceinline__ float qexpm1(float x)
+{
+    float p = 1.0f / 40320.0f;
+    p = fmaf(p, x, 1.0f / 5040.0f);
+    p = fmaf(p, x, 1.0f / 720.0f);
+    p = fmaf(p, x, 1.0f / 120.0f);
+    p = fmaf(p, x, 1.0f / 24.0f);
+    p = fmaf(p, x, 1.0f / 6.0f);
+    p = fmaf(p, x, 0.5f);
+    p = fmaf(p, x, 1.0f);
+    p = p * x;
+    const float e = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.0f;
+    return fabsf(x) < 0.5f ? p : e;
+}
+__device__ __forceinline__ double qexpm1(double x) { return expm1(x); }
+
+// FP32 sin and cos without branches: reduction by multiples of pi/2 with a
+// two-constant (Cody-Waite) split of pi/2, then the Taylor series of sin to
+// f^9 and cos to f^10 on |f| <= pi/4 (remainders < 2e-9).  Meant for the
+// moderate arguments of the thermal phase (|x| < 1e4).
+__device__ __forceinline__ void qsincos(float x, float* s, float* c)
+{
+    const float k = rintf(x * 0.636619772367581343f);
+    float f = fmaf(-k, 1.57079637050628662109375f, x);
+    f = fmaf(-k, -4.37113900018624283e-8f, f);
+    const float f2 = f * f;
+    float sp = -1.0f / 362880.0f;
+    sp = fmaf(sp, f2, 1.0f / 5040.0f);
+    sp = fmaf(sp, f2, -1.0f / 120.0f);
+    sp = fmaf(sp, f2, 1.0f / 6.0f);
+    sp = fmaf(-sp * f2, f, f);
+    float cp = -1.0f / 3628800.0f;
+    cp = fmaf(cp, f2, 1.0f / 40320.0f);
+    cp = fmaf(cp, f2, -1.0f / 720.0f);
+    cp = fmaf(cp, f2, 1.0f / 24.0f);
+    cp = fmaf(cp, f2, -0.5f);
+    cp = fmaf(cp, f2, 1.0f);
+    const int q = (int)k & 3;
+    const float ss = (q & 1) ? cp : sp, cc = (q & 1) ? sp : cp;
+    *s = (q & 2) ? -ss : ss;
+    *c = ((q + 1) & 2) ? -cc : cc;
+}
+__device__ __forceinline__ void qsincos(double x, double* s, double* c) { sincos(x, s, c); }
+
+// kappa_hat at temperature T: the constant kappa_hat >= 0, or, for -1, -2,
+// -3, the central, lower and upper fits to lattice data of the appendix
+// "Munich potential", 1 / (a x^{3/2} + b x + c x^{1/2} + d) with
+// x = T / T_c, T_c = 155 MeV; 0 where that denominator is not positive
+// (below the fits' range).  Evaluated once per step, in FP64.
+__device__ __forceinline__ double kappa_hat_at(double kappa_hat, double T)
+{
+    if (kappa_hat >= 0.0) return kappa_hat;
+    const int k = (int)(-kappa_hat);
+    const double a = k == 1 ? 0.00397 : k == 2 ? 0.00712 : 0.00272;
+    const double b = k == 1 ? -0.08341 : k == 2 ? -0.14262 : -0.05854;
+    const double c = k == 1 ? 0.98031 : k == 2 ? 1.55601 : 0.71513;
+    const double d = k == 1 ? -0.51889 : k == 2 ? -0.80712 : -0.38197;
+    const double x = T / 0.155;
+    const double sx = sqrt(x);
+    const double den = a * x * sx + b * x + c * sx + d;
+    return den > 0.0 ? 1.0 / den : 0.0;
+}
+
+// Sum of K values over the workgroup, every lane receives all K sums.
+template <int W, int K>
+__device__ __forceinline__ void block_sum_vec(double* x, double* red)
+{
+#pragma unroll
+    for (int i = 0; i < K; ++i) x[i] = wave_sum(x[i]);
+    if constexpr (W > 64) {
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int i = 0; i < K; ++i) red[i * (W / 64) + wave] = x[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < W / 64; ++w) s += red[i * (W / 64) + w];
+            x[i] = s;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) x[i] = uniform(x[i]);
+}
+
+// exp(-i (dt/2) [V_coulomb(r) + l(l+1)/(M r^2)]): the time-independent part
+// of the half-step factor (appendix "Munich potential").  The host computes
+// it in FP64 for every (l, colour) with l <= l_tab, shared by all
+// trajectories of a grid; a half-step reads the row of its (l, colour) (L1/L2
+// resident: few rows are in use at a time).
+template <class R, int N>
+__device__ __forceinline__ const cx<R>* phase_row(const GroupDesc& g, int l, int c)
+{
+    return static_cast<const cx<R>*>(g.phase) + (size_t)(2 * l + c) * N;
+}
+
+// FP32 exp(x) - 1 on |x| <= 1/2: the Taylor series to x^8 (remainder
+// < 2e-8 relative).  FP64 uses the library function.
+__device__ __forceinline__ float expm1_small(float x)
+{
+    float p = 1.0f / 40320.0f;
+    p = fmaf(p, x, 1.0f / 5040.0f);
+    p = fmaf(p, x, 1.0f / 720.0f);
+    p = fmaf(p, x, 1.0f / 120.0f);
+    p = fmaf(p, x, 1.0f / 24.0f);
+    p = fmaf(p, x, 1.0f / 6.0f);
+    p = fmaf(p, x, 0.5f);
+    p = fmaf(p, x, 1.0f);
+    return p * x;
+}
+__device__ __forceinline__ double expm1_small(double x) { return expm1(x); }
+
+// FP32 sin and cos on |x| <= pi/4: Taylor series to x^9 and x^10
+// (remainders < 2e-9).  FP64 uses the library function.
+__device__ __forceinline__ void sincos_small(float x, float* s, float* c)
+{
+    const float x2 = x * x;
+    float sp = -1.0f / 362880.0f;
+    sp = fmaf(sp, x2, 1.0f / 5040.0f);
+    sp = fmaf(sp, x2, -1.0f / 120.0f);
+    sp = fmaf(sp, x2, 1.0f / 6.0f);
+    *s = fmaf(-sp * x2, x, x);
+    float cp = -1.0f / 3628800.0f;
+    cp = fmaf(cp, x2, 1.0f / 40320.0f);
+    cp = fmaf(cp, x2, -1.0f / 720.0f);
+    cp = fmaf(cp, x2, 1.0f / 24.0f);
+    cp = fmaf(cp, x2, -0.5f);
+    *c = fmaf(cp, x2, 1.0f);
+}
+__device__ __forceinline__ void sincos_small(double x, double* s, double* c) { sincos(x, s, c); }
+
+// The half-step factor exp(-i V_eff(r_m) dt/2) of one time step is
+//   P_m exp(z r_m^2),   z = zr + i zi = -(dt/2) c (kappa + i gamma) T^3,
+// c = 1/2 (singlet) or 7/32 (octet), P_m the static phase (table row).  It is
+// applied as two diagonal factors: the real damping D_m = exp(zr r_m^2),
+// applied as u + (D_m - 1) u with D_m - 1 from expm1 so that its rounding is
+// relative to the (small) difference and does not bias the norm step after
+// step, and the phase C_m = P_m exp(i zi r_m^2), of modulus one.  The step is
+//   D C [DST kin DST] C D,
+// the bracket and C are unitary.  FP32-bulk renormalises C [DST kin DST] C
+// as a whole to the norm it receives, which also absorbs the modulus error of
+// C_m in FP32.  FAST: every argument is small (|zr| r^2 <= 1/2, |zi| r^2 <=
+// pi/4 on the whole grid: a per-step, wave-uniform decision), so short
+// series suffice.
+template <class R, bool GAMMA, bool FAST>
+struct HalfStep {
+    const cx<R>* row;
+    R dr, zr, zi;
+    __device__ __forceinline__ R r2(int m) const
+    {
+        const R rm = R(m) * dr;
+        return rm * rm;
+    }
+    __device__ __forceinline__ R em1(R x2) const
+    {
+        return FAST ? expm1_small(zr * x2) : qexpm1(zr * x2);
+    }
+    __device__ __forceinline__ cx<R> static_phase(int m) const { return ldg(row, m); }
+    __device__ __forceinline__ cx<R> phase(cx<R> p, R x2) const
+    {
+        if constexpr (GAMMA) {
+            R s, c;
+            if constexpr (FAST) sincos_small(zi * x2, &s, &c);
+            else qsincos(zi * x2, &s, &c);
+            return p * mk(c, s);
+        } else {
+            return p;
+        }
+    }
+    // the interface of a half-step factor: data loaded ahead for point m,
+    // then D_m - 1 and C_m
+    __device__ __forceinline__ cx<R> preload(int m) const { return static_phase(m); }
+    __device__ __forceinline__ void factors(int m, cx<R> pre, R& dm1, cx<R>& C) const
+    {
+        const R x2 = r2(m);
+        dm1 = em1(x2);
+        C = phase(pre, x2);
+    }
+};
+
+// The half-step factor of the isotropic KSU potential (appendix "Isotropic
+// KSU potential"), computed per point from the step's Debye mass m_D and
+// width coefficient c_I = alpha_s C_F T:
+//   V_R = min(V_KMS, V_vac(r_SB)) + l(l+1)/(M r^2),
+//   V_KMS = -(a/r)(1 + x) e^{-x} + 2 sigma r (1 - e^{-x})/x - sigma r e^{-x},
+//   V_I = -c_I phi(x),  x = m_D r,
+// D = exp(V_I dt/2), C = exp(-i V_R dt/2).  phi comes from a cubic Hermite
+// table of (phi, phi') on [0, 1/2] (spacing 1/8192) and [1/2, 64] (spacing
+// 1/256), and its asymptotic series beyond.  The point r = 0 (a boundary
+// value, always 0) gets the factor 1.
+constexpr double kKsuA = 0.409, kKsuSigma = 0.21;
+constexpr int kPhiFine = 4096, kPhiCoarse = 16256;   // intervals
+template <class R>
+struct HalfStepKSU {
+    const cx<R>* phi_tab;     // (phi, phi'): kPhiFine + 1 fine, then kPhiCoarse + 1
+    R dr, half_dt, md, cI, cent, vsb;
+    __device__ __forceinline__ cx<R> preload(int) const { return mk(R(0), R(0)); }
+    __device__ __forceinline__ R phi(R x) const
+    {
+        auto herm = [](R t, cx<R> p0, cx<R> p1, R h) QT_INL {
+            const R t2 = t * t, t3 = t2 * t;
+            return (R(2) * t3 - R(3) * t2 + R(1)) * p0.re + (t3 - R(2) * t2 + t) * h * p0.im +
+                   (R(3) * t2 - R(2) * t3) * p1.re + (t3 - t2) * h * p1.im;
+        };
+        if (x < R(0.5)) {
+            const R s = x * R(kPhiFine * 2);
+            const int i = (int)s;
+            return herm(s - R(i), ldg(phi_tab, i), ldg(phi_tab, i + 1), R(1.0 / (kPhiFine * 2)));
+        }
+        if (x < R(64)) {
+            const R s = (x - R(0.5)) * R(256);
+            const int i = (int)s;
+            const int k = kPhiFine + 1 + i;
+            return herm(s - R(i), ldg(phi_tab, k), ldg(phi_tab, k + 1), R(1.0 / 256.0));
+        }
+        const R q = R(1) / (x * x);
+        return R(1) - q * (R(2) + q * (R(8) + q * (R(144) + q * (R(5760) + q * R(403200)))));
+    }
+    __device__ __forceinline__ void factors(int m, cx<R>, R& dm1, cx<R>& C) const
+    {
+        const R r = R(m > 0 ? m : 1) * dr;
+        const R x = md * r;
+        const R e = exp(-x);
+        const R q = x > R(1e-4) ? -qexpm1(-x) / x : R(1) - x * (R(0.5) - x * R(1.0 / 6.0));
+        const R kms = -(R(kKsuA) / r) * (R(1) + x) * e + R(2 * kKsuSigma) * r * q - R(kKsuSigma) * r * e;
+        const R vr = (kms <= vsb ? kms : vsb) + cent / (r * r);
+        const R vi = -cI * phi(x);
+        R s, c;
+        qsincos(-half_dt * vr, &s, &c);
+        dm1 = m > 0 ? qexpm1(half_dt * vi) : R(0);
+        C = m > 0 ? mk(c, s) : mk(R(1), R(0));
+    }
+};
+
+// Per-step scalars of the KSU potential at temperature T: the one-loop
+// alpha_s(2 pi T) from alpha_s(5 GeV) = 0.2034 with 3 light flavours, the
+// Debye mass m_D = F T sqrt(N_c (1 + N_F/6) pi (4/3) alpha_s) and c_I =
+// alpha_s C_F T; no medium (0, 0) where T <= 0 or the coupling is not
+// positive (at and below the one-loop pole).
+__device__ __forceinline__ void ksu_medium(double T, double md_factor, double* md, double* cI)
+{
+    *md = 0.0;
+    *cI = 0.0;
+    if (!(T > 0.0)) return;
+    const double pi = 3.14159265358979323846;
+    const double inv = 1.0 / 0.2034 + (11.0 - 2.0) / (2.0 * pi) * log(2.0 * pi * T / 5.0);
+    if (!(inv > 0.0)) return;
+    const double as = 1.0 / inv;
+    *md = md_factor * T * sqrt(3.0 * 1.5 * pi * (4.0 / 3.0) * as);
+    *cI = as * (4.0 / 3.0) * T;
+}
+
+// First half-step: u <- C D u.  Returns this lane's part of sum |D u|^2 (the
+// norm the unitary block receives) when SUM; stores C_m in `fac` (this
+// lane's slots, no other lane reads them) when CACHE, and D_m - 1 in dm
+// (registers, for the second half-step).
+template <class R, int N, int W, class H, bool CACHE, bool SUM>
+__device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
+                                             const Lanes<N, W>& ln, cx<R>* fac, R* dm)
+{
+    constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
+    double acc = 0.0;
+    cx<R>* mine = fac + ln.t;
+    // table data first: every load in flight at once
+    cx<R> pr[2 * R1];
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        pr[Rr] = h.preload(ln.ja + Rr * T);
+        pr[R1 + Rr] = h.preload(ln.jb + Rr * T);
+    });
+    auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
+        cx<R> C;
+        h.factors(m, pr[E], dm[E], C);
+        const cx<R> w = u + scale(u, dm[E]);
+        if constexpr (SUM) acc += abs2d(w);
+        if constexpr (CACHE) mine[E * W] = C;
+        u = C * w;
+    };
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        apply(ln.ja + Rr * T, a[Rr], std::integral_constant<int, Rr>{});
+        apply(ln.jb + Rr * T, b[Rr], std::integral_constant<int, R1 + Rr>{});
+        if constexpr ((Rr & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    });
+    return acc;
+}
+
+// Second half-step: u <- D C u.  Adds this lane's sum |C u|^2 to x0 (when
+// SUM0) and sum |D C u|^2 to x1.
+template <class R, int N, int W, class H, bool CACHE, bool SUM0>
+__device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
+                                            const Lanes<N, W>& ln, const cx<R>* fac, const R* dm,
+                                            double& x0, double& x1)
+{
+    constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
+    const cx<R>* mine = fac + ln.t;
+    auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
+        cx<R> C;
+        if constexpr (CACHE) {
+            C = mine[E * W];
+        } else {
+            R unused;
+            h.factors(m, h.preload(m), unused, C);
+        }
+        const cx<R> w = C * u;
+        if constexpr (SUM0) x0 += abs2d(w);
+        u = w + scale(w, dm[E]);
+        x1 += abs2d(u);
+    };
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        apply(ln.ja + Rr * T, a[Rr], std::integral_constant<int, Rr>{});
+        apply(ln.jb + Rr * T, b[Rr], std::integral_constant<int, R1 + Rr>{});
+        if constexpr ((Rr & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
+// Calls f(GAMMA, FAST) with the two decisions as compile-time constants (the
+// decisions are wave-uniform: one scalar branch).
+template <class F>
+__device__ __forceinline__ void with_factor_kind(bool gamma, bool fast, F&& f)
+{
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (gamma) {
+        if (fast) f(T_{}, T_{});
+        else f(T_{}, F_{});
+    } else {
+        if (fast) f(F_{}, T_{});
+        else f(F_{}, F_{});
+    }
+}
+
+// u <- u + f u (f small: a relative correction)
+template <class R, int N, int W>
+__device__ __forceinline__ void add_scaled(cx<R>* a, cx<R>* b, R f)
+{
+    constexpr int R1 = Plan<N, W>::R1;
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        a[Rr] = a[Rr] + scale(a[Rr], f);
+        b[Rr] = b[Rr] + scale(b[Rr], f);
+    });
+}
+
+template <class R, int N, int W>
+__device__ __forceinline__ double sum_abs2(const cx<R>* a, const cx<R>* b)
+{
+    constexpr int R1 = Plan<N, W>::R1;
+    double acc = 0.0;
+    sfor<0, R1>([&](auto Rr) QT_INL { acc += abs2d(a[Rr]) + abs2d(b[Rr]); });
+    return acc;
+}
+
+// Writes the results of a finished trajectory (overlaps in FP64).
+template <class R, int N, int W>
+__device__ __forceinline__ void write_results(const GroupDesc& g, int64_t idx, const cx<R>* a,
+                                              const cx<R>* b, const Lanes<N, W>& ln, double* red,
+                                              int l, int c, int n_jumps, int status, int64_t steps,
+                                              double norm, double first_r, double min_gap)
+{
+    constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
+    // x[0..11]: re/im of the six dot products, x[12]: sum |u|^2, x[13]: sum r |u|^2
+    double x[14];
+#pragma unroll
+    for (int i = 0; i < 14; ++i) x[i] = 0.0;
+    const double* basis = g.basis;
+    auto acc = [&](int m, cx<R> u) QT_INL {
+        const double ur = (double)u.re, ui = (double)u.im;
+        const double w2 = ur * ur + ui * ui;
+        x[12] += w2;
+        x[13] += (double)m * g.dr * w2;
+#pragma unroll
+        for (int bb = 0; bb < 6; ++bb) {
+            const double ph = basis[bb * N + m];
+            x[2 * bb] += ph * ur;
+            x[2 * bb + 1] += ph * ui;
+        }
+    };
+    // one element at a time: the scheduler would otherwise issue every basis
+    // load at once and hold them all in registers
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        acc(ln.ja + Rr * T, a[Rr]);
+        __builtin_amdgcn_sched_barrier(0);
+        acc(ln.jb + Rr * T, b[Rr]);
+        __builtin_amdgcn_sched_barrier(0);
+    });
+    block_sum_vec<W, 14>(x, red);
+    if (threadIdx.x == 0) {
+        const qt_results& o = g.out;
+        constexpr int basis_l[6] = {0, 0, 1, 0, 1, 2};
+        const double nrm = x[12];
+#pragma unroll
+        for (int bb = 0; bb < 6; ++bb) {
+            double ov = 0.0, sv = 0.0;
+            if ((status == QT_TRAJ_OK || status == QT_TRAJ_NOJUMP) && c == QT_SINGLET &&
+                l == basis_l[bb] && nrm > 0.0) {
+                const double dr_ = g.dr * x[2 * bb], di_ = g.dr * x[2 * bb + 1];
+                ov = (dr_ * dr_ + di_ * di_) / (g.dr * nrm);
+                sv = g.init_overlap[bb] != 0.0 ? ov / g.init_overlap[bb] : ov;
+            }
+            if (o.overlap) o.overlap[6 * idx + bb] = ov;
+            if (o.survival) o.survival[6 * idx + bb] = sv;
+        }
+        if (o.norm) o.norm[idx] = norm;
+        if (o.first_r) o.first_r[idx] = first_r;
+        if (o.mean_r) o.mean_r[idx] = nrm > 0.0 ? x[13] / nrm : 0.0;
+        if (o.l) o.l[idx] = l;
+        if (o.color) o.color[idx] = c;
+        if (o.n_jumps) o.n_jumps[idx] = n_jumps;
+        if (o.status) o.status[idx] = status;
+        if (o.steps_done) o.steps_done[idx] = steps;
+        if (o.min_gap) o.min_gap[idx] = min_gap;
+    }
+    if (g.out.psi) {
+        double* dst = g.out.psi + (size_t)idx * 2 * N;
+        sfor<0, R1>([&](auto Rr) QT_INL {
+            const int ma = ln.ja + Rr * T, mb = ln.jb + Rr * T;
+            dst[2 * ma] = (double)a[Rr].re;
+            dst[2 * ma + 1] = (double)a[Rr].im;
+            dst[2 * mb] = (double)b[Rr].re;
+            dst[2 * mb + 1] = (double)b[Rr].im;
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+}
+
+// Results of a trajectory that cannot jump: those of the batch's zeroth
+// trajectory (paper: Sec. "Summary of QTraj execution", step 4, r_0 < rMin),
+// with its own first threshold r and gap r_min - r (its gap to every norm of
+// that evolution, the smallest being at the smallest norm).  The zeroth
+// trajectory runs as the first item of the same launch; a trajectory that
+// starts before it has finished is evolved instead, with the same results
+// (see the label at completion).
+template <int N, int W>
+__device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, double r, double r_min)
+{
+    const qt_results& z = g.zeroth;
+    const qt_results& o = g.out;
+    if (threadIdx.x == 0) {
+        if (o.norm) o.norm[idx] = z.norm[0];
+        if (o.first_r) o.first_r[idx] = r;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            if (o.overlap) o.overlap[6 * idx + q] = z.overlap[q];
+            if (o.survival) o.survival[6 * idx + q] = z.survival[q];
+        }
+        if (o.mean_r) o.mean_r[idx] = z.mean_r[0];
+        if (o.l) o.l[idx] = z.l[0];
+        if (o.color) o.color[idx] = z.color[0];
+        if (o.n_jumps) o.n_jumps[idx] = 0;
+        if (o.status) o.status[idx] = QT_TRAJ_NOJUMP;
+        if (o.steps_done) o.steps_done[idx] = z.steps_done[0];
+        if (o.min_gap) o.min_gap[idx] = r_min - r;
+    }
+    if (o.psi) {
+        double* dst = o.psi + (size_t)idx * 2 * N;
+        for (int m = threadIdx.x; m < 2 * N; m += W) dst[m] = z.psi[m];
+    }
+}
+
+// ------------------------------------------------------------ FUSED -------
+
+// At least two waves per SIMD: the register budget is 256 per lane (VGPRs
+// and AGPRs together), so that the allocator never trades a register or two
+// for half the occupancy.
+template <class R, int N, int W, int POT>
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fused_kernel(FusedArgs A)
+{
+    using PL = Plan<N, W>;
+    constexpr int R1 = PL::R1, T = PL::T;
+    // FP32-bulk renormalises the unitary block of every step (see below)
+    constexpr bool kRenorm = std::is_same<R, float>::value;
+    // exchange buffer of the transforms (FP32: see dst32), block-scan scratch
+    constexpr size_t kBufBytes = kRenorm ? dst32_buf_bytes<N, W>()
+                                         : sizeof(cx<R>) * (size_t)padded_len<N>();
+    __shared__ __attribute__((aligned(16))) char buf[kBufBytes];
+    __shared__ cx<double> wsum[W / 64];
+    __shared__ double red[14 * (W / 64)];
+    __shared__ int s_item;
+    __shared__ int s_zdone;
+    // per-lane cache of the phase factors C_m between the two half-steps of a
+    // step, kept when it still leaves room for two workgroups per CU
+    constexpr bool kCache = kBufBytes + sizeof(cx<R>) * N <= 80u * 1024u;
+    __shared__ cx<R> fac[kCache ? N : 1];
+
+    const Lanes<N, W> ln(threadIdx.x);
+    const cx<R>* tw = static_cast<const cx<R>*>(A.tw);
+    const cx<R>* prew = static_cast<const cx<R>*>(A.prew);
+
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (item >= A.n_items) break;
+        const GroupDesc& g = A.groups[uniform(A.item_group[item])];
+        const int64_t idx = uniform(A.item_index[item]);
+        const uint64_t stride = g.traj_id_stride ? g.traj_id_stride : 1u;
+        const uint64_t traj_id = g.traj_id0 + (uint64_t)idx * stride;
+
+        cx<R> a[R1], b[R1];
+        // FP32-bulk: the state is scl times the stored values.  The norm
+        // correction of a step is often below half an FP32 ulp, so that
+        // multiplying the values by it would change none of them and its
+        // sign, the same step after step, would add up; it is kept in FP64
+        // instead (and in the checkpoint) and folded into the values when
+        // it is large, at a jump and at the end.
+        double scl = 1.0;
+        int l, c, n_jumps, status;
+        int64_t step;
+        double r, first_r, min_gap, norm;
+        const bool resume = g.st != nullptr && g.st[idx].started;
+        if (resume) {
+            const TrajState s = g.st[idx];
+            if (s.done) continue;
+            const cx<R>* src = static_cast<const cx<R>*>(g.st_psi) + (size_t)idx * N;
+            sfor<0, R1>([&](auto Rr) QT_INL {
+                a[Rr] = src[ln.ja + Rr * T];
+                b[Rr] = src[ln.jb + Rr * T];
+            });
+            l = s.l; c = s.c; n_jumps = s.n_jumps; status = s.status; step = s.step;
+            r = s.r; first_r = s.first_r; min_gap = s.min_gap; norm = s.norm;
+            scl = s.scl;
+        } else {
+            // the zeroth trajectory of a batch has threshold 0: it never jumps
+            const U4 e0 = event_block(g.seed, traj_id, 0);
+            r = uniform(g.flags & kFlagZeroth ? 0.0 : uniform01(e0.w[2]));
+            if (g.zeroth.norm != nullptr) {
+                // has the batch's zeroth trajectory finished?  One decision
+                // for the whole workgroup, then each lane's own acquire
+                if (threadIdx.x == 0)
+                    s_zdone = __hip_atomic_load(g.zdone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                const int zd = __builtin_amdgcn_readfirstlane(s_zdone);
+                __syncthreads();
+                if (zd) {
+                    (void)__hip_atomic_load(g.zdone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    const double r_min = uniform(g.zeroth.min_gap[0]);
+                    if (r < r_min) {
+                        // below every norm of the no-jump evolution: this
+                        // trajectory is that evolution
+                        take_zeroth<N, W>(g, idx, r, r_min);
+                        continue;
+                    }
+                }
+            }
+            sfor<0, R1>([&](auto Rr) QT_INL {
+                const int ma = ln.ja + Rr * T, mb = ln.jb + Rr * T;
+                a[Rr] = mk(R(g.init_psi[2 * ma]), R(g.init_psi[2 * ma + 1]));
+                b[Rr] = mk(R(g.init_psi[2 * mb]), R(g.init_psi[2 * mb + 1]));
+                if constexpr ((Rr & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            });
+            l = g.init_l; c = g.init_color; n_jumps = 0; status = QT_TRAJ_OK; step = 0;
+            min_gap = __builtin_huge_val();
+            first_r = r;
+            norm = g.dr * block_sum<W>(sum_abs2<R, N, W>(a, b), red);
+            if (g.do_jumps && r > g.r_max) status = QT_TRAJ_RMAX;
+        }
+
+        // every per-trajectory scalar is identical on all lanes: say so
+        l = uniform(l); c = uniform(c); n_jumps = uniform(n_jumps); status = uniform(status);
+        step = uniform(step); r = uniform(r); norm = uniform(norm);
+        int64_t end = uniform(g.n_steps);
+        if (A.seg_steps > 0 && step + A.seg_steps < end) end = step + A.seg_steps;
+        if (l > g.l_tab) status = QT_TRAJ_LMAX;
+        const bool has_gamma = g.gamma_hat != 0.0;
+        // one potential per kernel: its own register allocation
+        constexpr bool ksu = POT == QT_POTENTIAL_KSU;
+        const cx<R>* ksu_tab = static_cast<const cx<R>*>(g.ksu_phi);
+        const double ksu_rsb = 1.25 / 0.1973269804;
+        const double ksu_vsb = -kKsuA / ksu_rsb + kKsuSigma * ksu_rsb;
+        const R dr = R(g.dr);
+        const double xmax = (double)(N - 1) * g.dr * (double)(N - 1) * g.dr;
+        int cur = 0;
+        scl = uniform(scl);
+        while (status == QT_TRAJ_OK && step < end) {
+            // lane-derived values are recomputed every step (see opaque_lane)
+            const Lanes<N, W> ls(opaque_lane(threadIdx.x));
+            const int64_t n = step;
+            const double t = g.tau_start + (double)n * g.dt;
+            const double Tn = temperature_at(g.tau, g.Ttab, g.n_tab, t, cur);
+            const double T3 = Tn * Tn * Tn;
+            const double cc = (c == QT_SINGLET) ? 0.5 : 7.0 / 32.0;
+            const double kh = kappa_hat_at(g.kappa_hat, Tn);
+            const R zr = R(-0.5 * g.dt * cc * kh * T3);
+            const R zi = R(-0.5 * g.dt * cc * g.gamma_hat * T3);
+            const cx<R>* row = opaque(phase_row<R, N>(g, l, c));
+            // FP64 always takes the library functions
+            const bool fast = !kRenorm || (fabs(-0.5 * g.dt * cc * kh * T3) * xmax <= 0.5 &&
+                                           fabs(-0.5 * g.dt * cc * g.gamma_hat * T3) * xmax <= 0.78);
+
+            R dm[Plan<N, W>::P];
+            double n_in = 0.0;
+            // the KSU potential's factors are computed per point; its
+            // per-step scalars are FP64
+            double md = 0.0, cI = 0.0;
+            if constexpr (ksu) ksu_medium(Tn, g.md_factor, &md, &cI);
+            const HalfStepKSU<R> hk{ksu_tab, dr, R(0.5 * g.dt), R(md), R(cI),
+                                    R((double)l * (double)(l + 1) / g.mass), R(ksu_vsb)};
+            if constexpr (ksu) {
+                n_in = first_half<R, N, W, HalfStepKSU<R>, kCache, kRenorm>(a, b, hk, ls, fac, dm);
+            } else {
+                with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
+                    const HalfStep<R, G, F> h{row, dr, zr, zi};
+                    n_in = first_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm>(a, b, h, ls, fac, dm);
+                });
+            }
+            if constexpr (kRenorm) {
+                const cx<double>* kin = static_cast<const cx<double>*>(g.kin);
+                dst32<N, W, true>(a, b, ls, buf, wsum, A.tw, kin);
+                dst32<N, W, false>(a, b, ls, buf, wsum, A.tw, nullptr);
+            } else {
+                const Kin<double>* kin = static_cast<const Kin<double>*>(g.kin);
+                cx<double> pw[Plan<N, W>::R1];
+                load_prew<double, N, W>(pw, prew, ls);
+                cx<double>* bd = reinterpret_cast<cx<double>*>(buf);
+                const cx<double>* tw_n = opaque(tw);
+                dst1<double, N, W, true>(a, b, pw, prew, ls, bd, wsum, tw_n, kin);
+                dst1<double, N, W, false>(a, b, pw, prew, ls, bd, wsum, opaque(tw_n), nullptr);
+            }
+            // x: sum |D u|^2 after the first half-step (the norm the unitary
+            // block receives), sum |C u|^2 (what it returns), sum |D C u|^2
+            double x[3] = {n_in, 0.0, 0.0};
+            if constexpr (ksu) {
+                second_half<R, N, W, HalfStepKSU<R>, kCache, kRenorm>(a, b, hk, ls, fac, dm, x[1], x[2]);
+            } else {
+                with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
+                    const HalfStep<R, G, F> h{opaque(row), dr, zr, zi};
+                    second_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm>(a, b, h, ls, fac, dm,
+                                                                          x[1], x[2]);
+                });
+            }
+            if constexpr (kRenorm) {
+                // the block C DST kin DST C is unitary: restore the norm it
+                // received (D commutes with the scaling)
+                block_sum_vec<W, 3>(x, red);
+                scl = uniform(scl * sqrt(x[0] / x[1]));
+                norm = g.dr * x[2] * scl * scl;
+                if (fabs(scl - 1.0) > 0x1p-10) {
+                    add_scaled<R, N, W>(a, b, R(scl - 1.0));
+                    scl = 1.0;
+                }
+            } else {
+                norm = g.dr * block_sum<W>(x[2], red);
+            }
+            step = n + 1;
+            if (!g.do_jumps) continue;
+            const double gap = fabs(norm - r);
+            if (gap < min_gap) min_gap = gap;
+            if (norm <= r) {
+                if (g.max_jumps >= 0 && n_jumps >= g.max_jumps) {
+                    status = QT_TRAJ_MAXJUMPS;
+                    break;
+                }
+                const U4 e = event_block(g.seed, traj_id, (int64_t)n_jumps + 1);
+                const double ul = uniform01(e.w[0]), uc = uniform01(e.w[1]);
+                l = (ul < (double)l / (double)(2 * l + 1)) ? l - 1 : l + 1;
+                c = (c == QT_OCTET) ? (uc < 2.0 / 7.0 ? QT_SINGLET : QT_OCTET) : QT_OCTET;
+                sfor<0, R1>([&](auto Rr) QT_INL {
+                    a[Rr] = scale(a[Rr], R(ls.ja + Rr * T) * dr);
+                    b[Rr] = scale(b[Rr], R(ls.jb + Rr * T) * dr);
+                });
+                const double s2 = g.dr * block_sum<W>(sum_abs2<R, N, W>(a, b), red);
+                const R f = R(1.0 / sqrt(s2));
+                sfor<0, R1>([&](auto Rr) QT_INL {
+                    a[Rr] = scale(a[Rr], f);
+                    b[Rr] = scale(b[Rr], f);
+                });
+                norm = g.dr * block_sum<W>(sum_abs2<R, N, W>(a, b), red);
+                scl = 1.0;
+                r = uniform(uniform01(e.w[2]));
+                n_jumps += 1;
+                l = uniform(l);
+                c = uniform(c);
+                if (l > g.l_tab) {
+                    status = QT_TRAJ_LMAX;
+                    break;
+                }
+            }
+        }
+        const bool done = status != QT_TRAJ_OK || step >= g.n_steps;
+        if (done && scl != 1.0) {
+            add_scaled<R, N, W>(a, b, R(scl - 1.0));
+            scl = 1.0;
+        }
+        if (done) {
+            // in a batch with the no-jump shortcut, a trajectory that ran to
+            // the end without a jump evolved exactly as the zeroth one: its
+            // threshold lies below every norm of that evolution
+            if (g.zeroth.norm != nullptr && status == QT_TRAJ_OK && n_jumps == 0)
+                status = QT_TRAJ_NOJUMP;
+            write_results<R, N, W>(g, idx, a, b, ln, red, l, c, n_jumps, status, step, norm,
+                                   first_r, min_gap);
+            if (g.flags & kFlagZeroth) {
+                // publish: every lane's writes first, then the flag
+                __threadfence();
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(g.zdone, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (g.st) {
+            // checkpoint (the final state too, so a job can return it)
+            {
+                cx<R>* dst = static_cast<cx<R>*>(g.st_psi) + (size_t)idx * N;
+                sfor<0, R1>([&](auto Rr) QT_INL {
+                    dst[ln.ja + Rr * T] = a[Rr];
+                    dst[ln.jb + Rr * T] = b[Rr];
+                });
+            }
+            if (threadIdx.x == 0) {
+                TrajState s;
+                s.step = step; s.l = l; s.c = c; s.n_jumps = n_jumps; s.status = status;
+                s.started = 1; s.done = done ? 1 : 0; s.pad0 = 0; s.pad1 = 0;
+                s.r = r; s.first_r = first_r; s.min_gap = min_gap; s.norm = norm;
+                s.scl = scl; s.pad2 = 0.0;
+                g.st[idx] = s;
+            }
+        }
+    }
+}
+
+
+template <class R, int N, int W, int POT>
+hipError_t launch_fused(const FusedArgs& a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((fused_kernel<R, N, W, POT>), dim3(grid), dim3(W), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class R, int N, int W, int POT>
+int occupancy_fused()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fused_kernel<R, N, W, POT>, W, 0) !=
+        hipSuccess)
+        return 0;
+    return blocks;
+}
+
+struct FusedEntry {
+    int prec, N, W;
+    fused_launcher launch;
+    int (*occ)();
+};
+
+}  // namespace qt

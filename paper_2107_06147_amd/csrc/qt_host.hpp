@@ -26,6 +26,8 @@ struct qt_context {
     // static phase tables exp(-i dt/2 V_static) per (l, colour), keyed by
     // (precision, N, L, mass, alpha_s, dt)
     std::map<std::vector<double>, void*> phase;
+    // (phi, phi') table of the KSU potential's imaginary part, per precision
+    std::map<int, void*> ksu_phi;
 };
 
 namespace qt {
@@ -74,6 +76,10 @@ double host_temperature(const double* tau, const double* T, int n, double t);
 
 qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* out);
 qt_status choose_variant(qt_context* ctx, int prec, int N, qt_context::Variant* out);
+// The fused kernel for (precision, N, potential): block size, launcher and
+// resident workgroups per CU (the tuned variant for the Munich potential).
+qt_status pick_launcher(qt_context* ctx, int prec, int N, int potential, int* W,
+                        fused_launcher* launch, int* slots_per_cu);
 
 // Device image of a set of groups: one allocation holding group descriptors
 // and every table they point to.  `kin` is converted to the precision.
@@ -87,6 +93,7 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
                         const std::vector<qt_results>& outs, bool with_Tn,
                         hipStream_t s, bool async_alloc, DeviceGroups* out);
 qt_status ensure_phase(qt_context* ctx, const HostBatch& hb, int prec, const void** out);
+qt_status ensure_ksu_table(qt_context* ctx, int prec, const void** out);
 
 // Device buffers for the per-trajectory results (no wave functions).
 struct ResultBuffers {

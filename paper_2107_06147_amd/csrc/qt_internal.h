@@ -14,6 +14,8 @@ struct TrajState {
     int32_t l, c, n_jumps, status;
     int32_t started, done, pad0, pad1;
     double  r, first_r, min_gap, norm;
+    double  scl;          // FP32-bulk: the state is scl times the stored values
+    double  pad2;
 };
 
 // One batch of trajectories that share physics, table and initial state.
@@ -39,6 +41,10 @@ struct GroupDesc {
     qt_results zeroth;        // no-jump trajectory's results (one entry, with
                               // psi), or all null: no shortcut
     int32_t*   zdone;         // set to 1 (release) once `zeroth` is complete
+    int32_t    potential;     // QT_POTENTIAL_*
+    int32_t    pad2;
+    double     md_factor;     // KSU: Debye-mass factor
+    const void* ksu_phi;      // KSU: (phi, phi') table, precision of the kernel
 };
 
 // Internal flag (above the public QT_FLAG_* bits): the group is the zeroth
@@ -65,6 +71,9 @@ int fused_variants(int prec, int N, int* W_out, int max_out);
 fused_launcher fused_get(int prec, int N, int W);
 // Occupancy of a variant: resident workgroups per CU.
 int fused_occupancy(int prec, int N, int W);
+// The variant compiled for the isotropic KSU potential at (precision, N):
+// its block size, launcher and resident workgroups per CU.
+bool fused_ksu_variant(int prec, int N, int* W, fused_launcher* launch, int* slots_per_cu);
 
 hipError_t launch_queue_reset(int32_t* q, hipStream_t s);
 // zeroes n int32 values (a fill kernel, safe under graph capture)

@@ -126,12 +126,11 @@ qt_status qt_job_create(qt_context* ctx, const qt_physics* phys, const qt_ttable
         qt_job_destroy(j);
         return s;
     };
-    qt_context::Variant v;
     qt_context::Tables t;
-    if ((st = choose_variant(ctx, j->prec, j->N, &v)) != QT_OK) return cleanup(st);
+    int slots = 0;
+    if ((st = pick_launcher(ctx, j->prec, j->N, phys->potential, &j->W, &j->launch, &slots)) != QT_OK)
+        return cleanup(st);
     if ((st = ensure_tables(ctx, j->prec, j->N, &t)) != QT_OK) return cleanup(st);
-    j->W = v.W;
-    j->launch = fused_get(j->prec, j->N, v.W);
     if ((st = alloc_results(j->n_traj, &j->res)) != QT_OK) return cleanup(st);
     const int64_t n = std::max<int64_t>(j->n_traj, 1);
     if (hipMalloc(reinterpret_cast<void**>(&j->st), n * sizeof(TrajState)) != hipSuccess ||
@@ -167,7 +166,7 @@ qt_status qt_job_create(qt_context* ctx, const qt_physics* phys, const qt_ttable
     j->args.tw = t.tw;
     j->args.prew = t.prew;
     j->args.seg_steps = segment_steps;
-    j->grid = (int)std::min<int64_t>(std::max<int64_t>(j->n_traj, 1), (int64_t)ctx->n_cu * v.slots_per_cu);
+    j->grid = (int)std::min<int64_t>(std::max<int64_t>(j->n_traj, 1), (int64_t)ctx->n_cu * slots);
     *out = j;
     return QT_OK;
 }

@@ -15,12 +15,12 @@ namespace qt {
 
 struct U4 { uint64_t w[4]; };
 
-__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
+__host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b)
 {
     return (uint64_t)(((unsigned __int128)a * b) >> 64);
 }
 
-__host__ __device__ inline U4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+__host__ __device__ __forceinline__ U4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                                             uint64_t k0, uint64_t k1)
 {
     const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
@@ -38,13 +38,13 @@ __host__ __device__ inline U4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c
     return o;
 }
 
-__host__ __device__ inline double uniform01(uint64_t w)
+__host__ __device__ __forceinline__ double uniform01(uint64_t w)
 {
     return ((double)(w >> 12) + 0.5) * (1.0 / 4503599627370496.0);
 }
 
 // Random block of event e (0 = start, e >= 1 = e-th jump) of a trajectory.
-__host__ __device__ inline U4 event_block(uint64_t seed, uint64_t traj_id, int64_t e)
+__host__ __device__ __forceinline__ U4 event_block(uint64_t seed, uint64_t traj_id, int64_t e)
 {
     return philox4x64_10((uint64_t)e + 1u, traj_id, 0u, 0u, seed, 0u);
 }

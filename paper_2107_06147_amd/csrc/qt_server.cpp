@@ -155,9 +155,10 @@ qt_status run_round(qt_server* s, int64_t* advanced)
     std::vector<int> gN;
     for (auto& q : s->running) {
         groups.push_back(q->dg.host[0]);
-        gN.push_back(q->hb.phys.N);
+        gN.push_back(2 * q->hb.phys.N + q->hb.phys.potential);
     }
-    // items of every running request, grouped by N, longest remaining first
+    // items of every running request, grouped by (N, potential) (keyed
+    // 2 N + potential: the kernels are specialised on both)
     std::vector<int> Ns;
     for (int N : gN)
         if (std::find(Ns.begin(), Ns.end(), N) == Ns.end()) Ns.push_back(N);
@@ -196,13 +197,15 @@ qt_status run_round(qt_server* s, int64_t* advanced)
     }
     for (size_t c = 0; c < Ns.size(); ++c) {
         if (!count[c]) continue;
-        qt_context::Variant v;
+        const int N = Ns[c] / 2, pot = Ns[c] % 2;
+        int W = 0, slots = 0;
+        fused_launcher launch = nullptr;
         qt_context::Tables t;
         qt_status st;
         {
             std::lock_guard<std::mutex> lk(s->ctx->mu);
-            if ((st = choose_variant(s->ctx, prec, Ns[c], &v)) != QT_OK) return st;
-            if ((st = ensure_tables(s->ctx, prec, Ns[c], &t)) != QT_OK) return st;
+            if ((st = pick_launcher(s->ctx, prec, N, pot, &W, &launch, &slots)) != QT_OK) return st;
+            if ((st = ensure_tables(s->ctx, prec, N, &t)) != QT_OK) return st;
         }
         FusedArgs a;
         a.groups = dgroups;
@@ -213,9 +216,9 @@ qt_status run_round(qt_server* s, int64_t* advanced)
         a.tw = t.tw;
         a.prew = t.prew;
         a.seg_steps = s->cfg.segment_steps;
-        const int grid = (int)std::min<int64_t>((int64_t)count[c], (int64_t)s->ctx->n_cu * v.slots_per_cu);
+        const int grid = (int)std::min<int64_t>((int64_t)count[c], (int64_t)s->ctx->n_cu * slots);
         QT_HIP(launch_queue_reset(a.queue, s->stream));
-        QT_HIP(fused_get(prec, Ns[c], v.W)(a, grid, s->stream));
+        QT_HIP(launch(a, grid, s->stream));
     }
     QT_HIP(hipStreamSynchronize(s->stream));
     // progress: read the state records back

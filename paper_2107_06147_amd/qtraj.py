@@ -25,6 +25,7 @@ QT_FORM_FUSED, QT_FORM_PLAIN = 0, 1
 QT_INIT_COULOMB, QT_INIT_GAUSSIAN, QT_INIT_ARRAY = 0, 1, 2
 QT_SINGLET, QT_OCTET = 0, 1
 QT_TRAJ_OK, QT_TRAJ_RMAX, QT_TRAJ_MAXJUMPS, QT_TRAJ_LMAX, QT_TRAJ_NOJUMP = 0, 1, 2, 3, 4
+QT_POTENTIAL_MUNICH, QT_POTENTIAL_KSU = 0, 1
 QT_FLAG_KINETIC_OFF = 1
 
 _D = C.POINTER(C.c_double)
@@ -36,7 +37,8 @@ class qt_physics(C.Structure):
     _fields_ = [("N", C.c_int32), ("L", C.c_double), ("dt", C.c_double), ("mass", C.c_double),
                 ("alpha_s", C.c_double), ("kappa_hat", C.c_double), ("gamma_hat", C.c_double),
                 ("deriv_type", C.c_int32), ("do_jumps", C.c_int32), ("max_jumps", C.c_int32),
-                ("r_max", C.c_double), ("flags", C.c_int32)]
+                ("r_max", C.c_double), ("flags", C.c_int32), ("potential", C.c_int32),
+                ("md_factor", C.c_double)]
 
 
 class qt_ttable(C.Structure):
@@ -150,7 +152,8 @@ def physics(cfg):
                       float(cfg["alpha_s"]), float(cfg["kappa_hat"]), float(cfg["gamma_hat"]),
                       int(cfg.get("deriv_type", 0)), int(cfg.get("do_jumps", 1)),
                       int(cfg.get("max_jumps", -1)), float(cfg.get("r_max", 1.0)),
-                      int(cfg.get("flags", 0)))
+                      int(cfg.get("flags", 0)), int(cfg.get("potential", 0)),
+                      float(cfg.get("md_factor", 1.0)))
 
 
 def ttable(cfg, keep):

@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_2107_06147_amd import qtraj as qt
 from paper_2107_06147_amd import workloads as W
-from tests.gpu_parity import compare, gpu_run
+from tests.gpu_parity import FP32_DELTA, compare, gpu_run
 
 pytestmark = pytest.mark.gpu
 
@@ -59,7 +59,7 @@ def test_shortcut_against_oracle(ctx, prec):
     # the shortcut decision compares the threshold with the zeroth's
     # smallest norm; away from that norm both sides decide alike
     r_min = np.min(ref["norm"][ref["status"] == oracle.STATUS_NOJUMP], initial=np.inf)
-    tol = 1e-9 if prec == F64 else 1e-4
+    tol = 1e-9 if prec == F64 else FP32_DELTA
     clear = np.abs(ref["first_r"] - r_min) > tol
     assert np.array_equal((ref["status"] == oracle.STATUS_NOJUMP)[clear],
                           (out["status"] == qt.QT_TRAJ_NOJUMP)[clear])

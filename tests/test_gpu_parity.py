@@ -188,3 +188,32 @@ def test_kappa_fit_against_oracle(ctx, fit, prec, form):
     out = gpu_run(ctx, cfg, prec, form=form)
     print("kappa fit", fit, prec, form, compare(ref, out, prec, label="kappa fit"),
           "jumps", int(ref["n_jumps"].sum()))
+
+
+# --------------------------------------------------- isotropic KSU potential
+
+@pytest.mark.parametrize("prec,form", [(F64, FUSED), (F64, PLAIN), (F32, FUSED)])
+def test_ksu_potential_against_oracle(ctx, prec, form):
+    """The isotropic KSU potential (singlet, no jumps) along a Bjorken
+    cooling from 0.5 GeV, Coulomb 1S and Gaussian l = 1 starts: every
+    trajectory matches the oracle."""
+    tau, T = W.bjorken_table(0.5, 0.6, 0.2, 300)
+    for init in (dict(init_kind=W.INIT_COULOMB), dict(init_kind=W.INIT_GAUSSIAN, init_l=1,
+                                                      init_width=2.0)):
+        cfg = W.base(N=512, L=20.0, dt=0.002, potential=W.POTENTIAL_KSU, md_factor=1.2,
+                     do_jumps=0, kappa_hat=0.0, n_traj=3, seed=8, tau=tau, T=T,
+                     tau_start=float(tau[0]), T_final=0.2, max_steps=700, **init)
+        ref = oracle.run(cfg, want_psi=True)
+        out = gpu_run(ctx, cfg, prec, form=form)
+        print("ksu", prec, form, init["init_kind"], compare(ref, out, prec, label="ksu"),
+              "norm", float(ref["norm"][0]))
+        assert ref["norm"][0] < 0.999          # the width acted
+
+
+def test_ksu_rejects_jumps_and_octet(ctx):
+    cfg = W.base(N=512, L=20.0, potential=W.POTENTIAL_KSU, n_traj=2, **W.constant_T(0.3, 10))
+    with pytest.raises(qt.QtError):
+        gpu_run(ctx, cfg, F64)                                   # do_jumps = 1
+    with pytest.raises(qt.QtError):
+        gpu_run(ctx, dict(cfg, do_jumps=0, init_color=W.OCTET, init_kind=W.INIT_GAUSSIAN,
+                          init_width=1.0), F64)
