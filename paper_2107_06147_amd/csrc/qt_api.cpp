@@ -329,6 +329,24 @@ qt_status prepare(const qt_physics* p, const qt_ttable* tt, const qt_init* in, c
 
 // -------------------------------------------------- per-N device tables ---
 
+// Rounds a unit complex number to FP32 choosing, among the neighbours within
+// one ulp per component, the one whose modulus is closest to 1.
+static void round_unit_f32(double c, double s, float* out)
+{
+    const float c0 = (float)c, s0 = (float)s;
+    float bc = c0, bs = s0;
+    double be = std::fabs((double)c0 * c0 + (double)s0 * s0 - 1.0);
+    const float cs[3] = {std::nextafter(c0, -2.f), c0, std::nextafter(c0, 2.f)};
+    const float ss[3] = {std::nextafter(s0, -2.f), s0, std::nextafter(s0, 2.f)};
+    for (float ci : cs)
+        for (float si : ss) {
+            const double e = std::fabs((double)ci * ci + (double)si * si - 1.0);
+            if (e < be) { be = e; bc = ci; bs = si; }
+        }
+    out[0] = bc;
+    out[1] = bs;
+}
+
 qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* out)
 {
     auto key = std::make_pair(prec, N);
@@ -355,6 +373,9 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
         // FP32 [FFT twiddles of length M = N/2 | exp(-i pi j/N), j < M],
         // FP64 [FFT twiddles, DST-I weights of length M | the same of length N]
         const int M = N / 2;
+        // (each component rounded to nearest: choosing the neighbour of
+        // modulus closest to 1 instead trades the modulus error for a
+        // larger phase error, which the steps accumulate the same way)
         std::vector<float> f(4 * (size_t)M);
         for (int m = 0; m < M; ++m) {
             f[2 * m] = (float)std::cos(2.0 * kPi * m / M);
@@ -482,23 +503,6 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // Highest l with a tabulated static phase.
 constexpr int kLTab = 255;
 
-// Rounds a unit complex number to FP32 choosing, among the neighbours within
-// one ulp per component, the one whose modulus is closest to 1.
-static void round_unit_f32(double c, double s, float* out)
-{
-    const float c0 = (float)c, s0 = (float)s;
-    float bc = c0, bs = s0;
-    double be = std::fabs((double)c0 * c0 + (double)s0 * s0 - 1.0);
-    const float cs[3] = {std::nextafter(c0, -2.f), c0, std::nextafter(c0, 2.f)};
-    const float ss[3] = {std::nextafter(s0, -2.f), s0, std::nextafter(s0, 2.f)};
-    for (float ci : cs)
-        for (float si : ss) {
-            const double e = std::fabs((double)ci * ci + (double)si * si - 1.0);
-            if (e < be) { be = e; bc = ci; bs = si; }
-        }
-    out[0] = bc;
-    out[1] = bs;
-}
 
 // exp(-i (dt/2) [V_coulomb(r_m) + l(l+1)/(M r_m^2)]) for l = 0..kLTab and
 // both colours (appendix "Munich potential"), rows [(2 l + c) N + m].
@@ -637,18 +641,16 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         std::memcpy(&blob[o[g].tau], h.tau.data(), h.tau.size() * 8);
         std::memcpy(&blob[o[g].T], h.T.data(), h.T.size() * 8);
         if (o[g].own_kin && f32) {
-            // in the output order of the FP32 sine transform: entry n < N/2
-            // is the factor of the odd output that the half-length cosine
-            // transform leaves in slot n, k = 4n + 1 (times 1/2) below N/4
-            // and k = 2N - 4n - 1 (times -1/2) above; entry N/2 + q that of
-            // the even output k = 2q
+            // in the slot order of the FP32 kinetic block (qt_dst32.hpp):
+            // entry n < N/2 is conj(K_k)/4 for the odd output k that the
+            // half-length cosine transform leaves in slot n (k = 4n + 1 below
+            // N/4, 2N - 4n - 1 above), entry N/2 + q is K_{2q}
             double* k = reinterpret_cast<double*>(&blob[o[g].kin]);
             const int M = N / 2;
             for (int n = 0; n < M; ++n) {
                 const int ko = n < M / 2 ? 4 * n + 1 : 2 * N - 4 * n - 1;
-                const double so = n < M / 2 ? 0.5 : -0.5;
-                k[2 * n] = so * (*h.kin)[2 * ko];
-                k[2 * n + 1] = so * (*h.kin)[2 * ko + 1];
+                k[2 * n] = 0.25 * (*h.kin)[2 * ko];
+                k[2 * n + 1] = -0.25 * (*h.kin)[2 * ko + 1];
                 k[2 * (M + n)] = (*h.kin)[4 * n];
                 k[2 * (M + n) + 1] = (*h.kin)[4 * n + 1];
             }

@@ -27,11 +27,13 @@
 //   F_{4n+1} = v_n / 2 (n < M/2),  F_{2N-4n-1} = -v_n / 2 (n >= M/2).
 // The inverse DFT is conj(FFT(conj V)).
 //
+// A step's kinetic block applies S K S; the second transform runs as the
+// transpose of the first (kin_block32), so neither leaves its slots.
+//
 // Tables (one block, see ensure_tables): FP32 [FFT twiddles of length M |
 // e^{-i pi j/N}, j < M], then FP64 [FFT twiddles of length M | DST-I weights
-// of length M | FFT twiddles of length N | DST-I weights of length N].
-// Kinetic factors in output order (cx<double>): entry n < M the factor of
-// the odd output in slot n with its sign and 1/2, entry M + q that of F_{2q}.
+// of length M | FFT twiddles of length N | DST-I weights of length N].  The
+// kinetic factors are in the slot order of kin_block32 (below).
 #pragma once
 #include "qt_device.hpp"
 
@@ -73,8 +75,8 @@ __device__ __forceinline__ cx<float> mulk(cx<float> f, cx<double> k)
     return mk((float)(re * k.re - im * k.im), (float)(re * k.im + im * k.re));
 }
 
-// LDS bytes of the exchange buffer (and of the block-scan scratch) that the
-// FP32 transform of length N on W lanes needs.
+// LDS bytes of the exchange buffer that the FP32 kinetic block of length N
+// on W lanes needs.
 template <int N, int W>
 constexpr size_t dst32_buf_bytes()
 {
@@ -82,19 +84,36 @@ constexpr size_t dst32_buf_bytes()
                               : sizeof(cx<double>) * (size_t)padded_len<N>();
 }
 
-// On entry a/b hold x in the mirror layout of length N; on exit F (times the
-// kinetic factor of each output if KIN) in the same layout.  buf: LDS of
-// dst32_buf_bytes<N, W>(); wsum: W/64 cx<double> of LDS.
-template <int N, int W, bool KIN>
-__device__ __forceinline__ void dst32(cx<float>* a, cx<float>* b, const Lanes<N, W>& ln_in,
-                                      void* buf, cx<double>* wsum, const void* tables,
-                                      const cx<double>* __restrict__ kin)
+// The kinetic block of a step, S diag(K) S x with S the DST-I of length N
+// (S S = (N/2) I; K carries 2/N).  S = P diag(C, D) B: B the pair
+// butterflies, C the cosine transform (odd outputs), D the half-length
+// DST-I (even outputs), P the placement of the outputs by k.  S is
+// symmetric, so the second transform is the transpose of the first, B^T
+// diag(C^T, D^T) P^T, and P^T P = I: the outputs never leave the slots in
+// which the first transform leaves them.  C^T: the same FFT (the DFT matrix
+// is symmetric) and the transposed mixing, a+'_M = 2 U_0,
+//   a+'_i = i conj(w_i) U_{M-i} - i w_i U_i   (w_i = e^{i pi i/N}),
+// with U the inverse DFT of the slots; D^T = D; B^T = B.  With o = FFT(conj
+// V) = conj(v) after the first FFT, the slot factor (1/2)^2 K_k of the
+// odd outputs and U = conj(FFT(conj(u))) fold into one multiply of o by
+// conj(K_k)/4 before the second FFT.  The kinetic table is in slot order:
+// entry n < M is conj(K_k)/4 for the odd output k of slot n, entry M + q
+// is K_{2q}.
+// On entry a/b hold x in the mirror layout of length N, on exit the result
+// in the same layout.  buf: LDS of dst32_buf_bytes<N, W>(); wsum: W/64
+// cx<double> of LDS.
+template <int N, int W>
+__device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const Lanes<N, W>& ln_in,
+                                            void* buf, cx<double>* wsum, const void* tables,
+                                            const cx<double>* __restrict__ kin)
 {
     using PL = Plan<N, W>;
     constexpr int R1 = PL::R1, T = PL::T;
+    constexpr int M = N / 2;
     const Dst32Tables<N> tb(opaque(static_cast<const char*>(tables)));
     if constexpr (PL::P < 8) {
-        // widened: dst1 of length N in FP64
+        // widened: dst1 of length N in FP64, the kinetic factors in between
+        // (natural order from the slot-ordered table)
         const Lanes<N, W> ln(opaque_lane(ln_in.t));
         cx<double> A[R1], B[R1], pw[R1];
         sfor<0, R1>([&](auto Rr) QT_INL {
@@ -102,36 +121,33 @@ __device__ __forceinline__ void dst32(cx<float>* a, cx<float>* b, const Lanes<N,
             B[Rr] = widen(b[Rr]);
         });
         load_prew<double, N, W>(pw, tb.pre64, ln);
-        dst1<double, N, W, false>(A, B, pw, tb.pre64, ln, static_cast<cx<double>*>(buf), wsum,
-                                  tb.tw64, nullptr);
-        // output k's factor in output order: even k at M + k/2, odd k at the
-        // slot n of the half-length cosine transform (with its sign and 1/2)
+        cx<double>* bd = static_cast<cx<double>*>(buf);
+        dst1<double, N, W, false>(A, B, pw, tb.pre64, ln, bd, wsum, tb.tw64, nullptr);
         auto kfac = [&](int k) QT_INL {
-            constexpr int M = N / 2;
-            if (!KIN) return mk(1.0, 0.0);
             if ((k & 1) == 0) return ldg(kin, (uint32_t)(M + k / 2));
-            const bool lo = ((k - 1) & 3) == 0;
-            const int n = lo ? (k - 1) / 4 : (2 * N - 1 - k) / 4;
+            const int n = ((k - 1) & 3) == 0 ? (k - 1) / 4 : (2 * N - 1 - k) / 4;
             const cx<double> f = ldg(kin, (uint32_t)n);
-            return lo ? mk(2.0 * f.re, 2.0 * f.im) : mk(-2.0 * f.re, -2.0 * f.im);
+            return mk(4.0 * f.re, -4.0 * f.im);
         };
         sfor<0, R1>([&](auto Rr) QT_INL {
-            const cx<double> ka = kfac(ln.ja + Rr * T), kb = kfac(ln.jb + Rr * T);
-            a[Rr] = narrow(A[Rr] * ka);
-            b[Rr] = narrow(B[Rr] * kb);
+            A[Rr] = A[Rr] * kfac(ln.ja + Rr * T);
+            B[Rr] = B[Rr] * kfac(ln.jb + Rr * T);
         });
-        return;
+        dst1<double, N, W, false>(A, B, pw, tb.pre64, ln, bd, wsum, opaque(tb.tw64), nullptr);
+        sfor<0, R1>([&](auto Rr) QT_INL {
+            a[Rr] = narrow(A[Rr]);
+            b[Rr] = narrow(B[Rr]);
+        });
     } else {
-        constexpr int M = N / 2;
         using PH = Plan<M, W>;
         constexpr int H = PH::R1;           // = R1 / 2; the same T
         static_assert(PH::T == T && 2 * H == R1, "half-length plan");
         const Lanes<M, W> ln(opaque_lane(ln_in.t));
         const bool lane0 = ln.t == 0;
-        // pairs (m, N - m) -> a+ (FP32) and a- (FP64) in the mirror layout of
-        // length M.  Lanes t > 0: m = t + rT pairs with b[R1-1-r], m = T - t
-        // + rT with a[R1-1-r].  Lane 0: m = rT pairs with (R1 - r) T
-        // (itself at 0, where x = 0), m = W + rT with W + (R1-1-r) T.
+        // B: pairs (m, N - m) -> a+ (FP32) and a- (FP64) in the mirror layout
+        // of length M.  Lanes t > 0: m = t + rT pairs with b[R1-1-r], m = T - t
+        // + rT with a[R1-1-r].  Lane 0: m = rT pairs with (R1 - r) T (itself
+        // at 0, where x = 0), m = W + rT with W + (R1-1-r) T.
         cx<float> ap[H], bp[H];
         cx<double> am[H], bm[H];
         sfor<0, H>([&](auto Rr) QT_INL {
@@ -153,11 +169,11 @@ __device__ __forceinline__ void dst32(cx<float>* a, cx<float>* b, const Lanes<N,
                 bm[r] = widen(b[r]) - widen(b[R1 - 1 - r]);
             });
         }
-        // odd outputs: FFT input conj(V_j) = e^{-i pi j/N} (conj(a+_{M-j})
-        // + i conj(a+_j)), in the mirror layout of length M (v[r] at
-        // j = ja + rT, v[H + r] at j = jb + rT).  Lanes t > 0: the mirror
-        // M - j of ja + rT is jb + (H-1-r) T and vice versa; lane 0: rT
-        // pairs with (H - r) T, and V_0 = 2 a+_M.
+        // C: FFT input conj(V_j) = e^{-i pi j/N} (conj(a+_{M-j}) + i
+        // conj(a+_j)) in the mirror layout of length M (v[r] at j = ja + rT,
+        // v[H + r] at j = jb + rT).  Lanes t > 0: the mirror M - j of ja + rT
+        // is jb + (H-1-r) T and vice versa; lane 0: rT pairs with (H - r) T,
+        // and V_0 = 2 a+_M.
         cx<float> v[PH::P];
         {
             const cx<float>* wd = opaque(tb.wd);
@@ -178,48 +194,87 @@ __device__ __forceinline__ void dst32(cx<float>* a, cx<float>* b, const Lanes<N,
                 });
             }
         }
+        cx<float>* b32 = static_cast<cx<float>*>(buf);
         {
             PassTwiddles<float, M, W, 0> none;
-            fft_passes<float, M, W, 0>(v, ln, static_cast<cx<float>*>(buf), opaque(tb.tw32), none);
+            fft_passes<float, M, W, 0>(v, ln, b32, opaque(tb.tw32), none);
         }
-        // even outputs: dst1 of length M in FP64 (kinetic factors of F_{2q}
-        // at M + q)
+        // slots n (v[r] at n = ja + rT, v[H + r] at jb + rT) times conj(K)/4
+        {
+            const cx<double>* kn = opaque(kin);
+            sfor<0, H>([&](auto Rr) QT_INL {
+                constexpr int r = Rr;
+                v[r] = mulk(v[r], ldg(kn, (uint32_t)(ln.ja + r * T)));
+                v[H + r] = mulk(v[H + r], ldg(kn, (uint32_t)(ln.jb + r * T)));
+            });
+        }
+        {
+            PassTwiddles<float, M, W, 0> none;
+            fft_passes<float, M, W, 0>(v, ln, b32, opaque(tb.tw32), none);
+        }
+        // C^T: U = conj(v); a+'_j = i (e_j U_{M-j} - conj(e_j) U_j), e_j =
+        // e^{-i pi j/N}; a+'_M = 2 U_0 (lane 0)
+        {
+            const cx<float>* wd = opaque(tb.wd);
+            auto tmix = [](cx<float> e, cx<float> um, cx<float> u) QT_INL {
+                // i (e conj(um') - conj(e) conj(u')) with um', u' the FFT outputs
+                const cx<float> p = e * conjf(um), q = conjf(e) * conjf(u);
+                const cx<float> d = p - q;
+                return mk(-d.im, d.re);
+            };
+            sfor<0, H>([&](auto Rr) QT_INL {
+                constexpr int r = Rr;
+                ap[r] = tmix(ldg(wd, ln.ja + r * T), v[H + H - 1 - r], v[r]);
+                bp[r] = tmix(ldg(wd, ln.jb + r * T), v[H - 1 - r], v[H + r]);
+            });
+            if (lane0) {
+                sfor<0, H>([&](auto Rr) QT_INL {
+                    constexpr int r = Rr;
+                    if constexpr (r == 0) {
+                        ap[0] = mk(0.0f, 0.0f);
+                    } else {
+                        ap[r] = tmix(ldg(wd, r * T), v[H - r], v[r]);
+                    }
+                    bp[r] = tmix(ldg(wd, W + r * T), v[H + H - 1 - r], v[H + r]);
+                });
+            }
+        }
+        const cx<float> pM = mk(2.0f * v[0].re, -2.0f * v[0].im);
+        // D, the kinetic factors of the even outputs, D^T = D, in FP64
         {
             cx<double> pw[H];
             load_prew<double, M, W>(pw, tb.pre64h, ln);
-            dst1<double, M, W, KIN>(am, bm, pw, tb.pre64h, ln, static_cast<cx<double>*>(buf), wsum,
-                                    opaque(tb.tw64h),
-                                    KIN ? reinterpret_cast<const Kin<double>*>(kin + M) : nullptr);
+            cx<double>* b64 = static_cast<cx<double>*>(buf);
+            dst1<double, M, W, true>(am, bm, pw, tb.pre64h, ln, b64, wsum, opaque(tb.tw64h),
+                                     reinterpret_cast<const Kin<double>*>(kin + M));
+            dst1<double, M, W, false>(am, bm, pw, tb.pre64h, ln, b64, wsum, opaque(tb.tw64h),
+                                      nullptr);
         }
-        // every output to its place k in LDS, then back in the mirror layout
-        // of length N.  Slot n = ja + rT of the cosine transform lies below
-        // M/2 exactly when r < H/2 (ja, jb < T and (H/2) T = M/2).
-        cx<float>* xb = static_cast<cx<float>*>(buf);
-        sfor<0, H>([&](auto Rr) QT_INL {
-            constexpr int r = Rr;
-            constexpr bool low = r < H / 2;
-            const int na = ln.ja + r * T, nb = ln.jb + r * T;
-            const int ka = low ? 4 * na + 1 : 2 * N - 4 * na - 1;
-            const int kb = low ? 4 * nb + 1 : 2 * N - 4 * nb - 1;
-            const cx<float> fa = conjf(v[r]), fb = conjf(v[H + r]);
-            if constexpr (KIN) {
-                xb[pad(ka)] = mulk(fa, ldg(kin, (uint32_t)na));
-                xb[pad(kb)] = mulk(fb, ldg(kin, (uint32_t)nb));
-            } else {
-                xb[pad(ka)] = low ? scale(fa, 0.5f) : scale(fa, -0.5f);
-                xb[pad(kb)] = low ? scale(fb, 0.5f) : scale(fb, -0.5f);
-            }
-            xb[pad(2 * na)] = narrow(am[r]);
-            xb[pad(2 * nb)] = narrow(bm[r]);
-        });
-        __syncthreads();
-        const cx<float>* sa = xb + pad(ln_in.ja);
-        const cx<float>* sb = xb + pad(ln_in.jb);
-        sfor<0, R1>([&](auto Rr) QT_INL {
-            a[Rr] = sa[padc<Rr * T>()];
-            b[Rr] = sb[padc<Rr * T>()];
-        });
-        __syncthreads();
+        // B^T: x_m = a+'_m + a-'_m, x_{N-m} = a+'_m - a-'_m, x_{N/2} = a+'_M
+        auto plus = [](cx<float> p, cx<double> q) QT_INL { return narrow(widen(p) + q); };
+        auto minus = [](cx<float> p, cx<double> q) QT_INL { return narrow(widen(p) - q); };
+        if (lane0) {
+            sfor<0, H>([&](auto Rr) QT_INL {
+                constexpr int r = Rr;
+                if constexpr (r == 0) {
+                    a[0] = mk(0.0f, 0.0f);
+                } else {
+                    a[r] = plus(ap[r], am[r]);
+                    a[R1 - r] = minus(ap[r], am[r]);
+                }
+                b[r] = plus(bp[r], bm[r]);
+                b[R1 - 1 - r] = minus(bp[r], bm[r]);
+            });
+            a[H] = pM;
+        } else {
+            sfor<0, H>([&](auto Rr) QT_INL {
+                constexpr int r = Rr;
+                a[r] = plus(ap[r], am[r]);
+                b[R1 - 1 - r] = minus(ap[r], am[r]);
+                b[r] = plus(bp[r], bm[r]);
+                a[R1 - 1 - r] = minus(bp[r], bm[r]);
+            });
+        }
     }
 }
 

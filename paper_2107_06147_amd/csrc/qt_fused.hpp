@@ -622,9 +622,7 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
                 });
             }
             if constexpr (kRenorm) {
-                const cx<double>* kin = static_cast<const cx<double>*>(g.kin);
-                dst32<N, W, true>(a, b, ls, buf, wsum, A.tw, kin);
-                dst32<N, W, false>(a, b, ls, buf, wsum, A.tw, nullptr);
+                kin_block32<N, W>(a, b, ls, buf, wsum, A.tw, static_cast<const cx<double>*>(g.kin));
             } else {
                 const Kin<double>* kin = static_cast<const Kin<double>*>(g.kin);
                 cx<double> pw[Plan<N, W>::R1];
