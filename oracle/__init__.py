@@ -111,6 +111,11 @@ def lib():
         L.qto_kappa_hat.restype = C.c_double
         L.qto_ksu_phi.argtypes = [C.c_double]
         L.qto_ksu_phi.restype = C.c_double
+        L.qto_potential.argtypes = [C.POINTER(_Physics), C.c_double, C.c_int32, C.c_int32,
+                                    C.c_double, _D, _D]
+        L.qto_potential.restype = None
+        L.qto_kinetic_energy.argtypes = [C.POINTER(_Physics), C.c_int32]
+        L.qto_kinetic_energy.restype = C.c_double
         _lib = L
     return _lib
 
@@ -253,3 +258,42 @@ def kappa_hat(kappa_hat_param, T):
 def ksu_phi(a):
     """phi(a) of the imaginary part of the isotropic KSU potential."""
     return float(lib().qto_ksu_phi(float(a)))
+
+
+def potential(cfg, r, l, color=SINGLET, T=0.0):
+    """(V_R, V_I) of the configured potential at r."""
+    p = _physics(cfg)
+    vr, vi = C.c_double(), C.c_double()
+    lib().qto_potential(C.byref(p), float(r), int(l), int(color), float(T), C.byref(vr), C.byref(vi))
+    return vr.value, vi.value
+
+
+def eigen_basis(cfg):
+    """Vacuum eigenstates 1S, 2S, 1P, 3S, 2P, 1D (Sec. "Using the built-in
+    eigensolvers"): the eigenvectors of the discrete Hamiltonian that the
+    evolution uses, at T = 0 for a singlet, H = T_kin + V with
+      T_kin = (2/N) S diag(E_k) S,  S_mk = sin(pi m k / N),  m, k = 1..N-1,
+    (E_k the kinetic energy of sine mode k, Sec. "Derivative types") and V the
+    potential plus the centrifugal term at r_m = m dr.  H is built as a dense
+    FP64 matrix and diagonalised (numpy.linalg.eigh); state n_r of angular
+    momentum l is the (n_r + 1)-th lowest.  Each state is normalised to
+    dr sum u_m^2 = 1 with u_1 > 0.  Returns (energies [6], basis [6, N])."""
+    N = int(cfg["N"])
+    dr = float(cfg["L"]) / N
+    p = _physics(cfg)
+    m = np.arange(1, N)
+    S = np.sin(np.pi * np.outer(m, m) / N)
+    E = np.array([lib().qto_kinetic_energy(C.byref(p), int(k)) for k in m])
+    Tk = (2.0 / N) * ((S * E) @ S)
+    energies = np.zeros(6)
+    basis = np.zeros((6, N))
+    for l, slots in ((0, (0, 1, 3)), (1, (2, 4)), (2, (5,))):
+        V = np.array([potential(cfg, j * dr, l)[0] for j in m])
+        w, v = np.linalg.eigh(Tk + np.diag(V))
+        for nr, b in enumerate(slots):
+            u = v[:, nr] / np.sqrt(dr * np.sum(v[:, nr] ** 2))
+            if u[0] < 0:
+                u = -u
+            energies[b] = w[nr]
+            basis[b, 1:] = u
+    return energies, basis

@@ -328,6 +328,18 @@ static void munich_potential(const qto_physics* p, double r, int32_t l, int32_t 
 }
 
 /* Hydrogen-like radial function u = r R_nl with Bohr radius a0. */
+/* The potential V_R + i V_I at r for angular momentum l and colour c at
+ * temperature T, and the kinetic energy of sine mode k: the two parts of
+ * the Hamiltonian, exported for the vacuum eigenstates (Sec. "Using the
+ * built-in eigensolvers"). */
+void qto_potential(const qto_physics* p, double r, int32_t l, int32_t c, double T,
+                   double* VR, double* VI)
+{
+    munich_potential(p, r, l, c, T, VR, VI);
+}
+
+double qto_kinetic_energy(const qto_physics* p, int32_t k) { return kinetic_energy(p, k); }
+
 static double hydrogen_u(int32_t n, int32_t l, double a0, double r)
 {
     double x = r / a0;

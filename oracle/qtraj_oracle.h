@@ -124,6 +124,12 @@ int    qto_basis_state(int32_t N, double L, double mass, double alpha_s,
 double qto_temperature(const qto_ttable* tt, double t);
 double qto_kappa_hat(double kappa_hat, double T);
 double qto_ksu_phi(double a);
+/* V_R + i V_I of the configured potential at r (l, colour c, temperature
+ * T), and the kinetic energy of sine mode k (GeV): the two parts of the
+ * Hamiltonian, for the vacuum eigenstates. */
+void   qto_potential(const qto_physics* p, double r, int32_t l, int32_t c, double T,
+                     double* VR, double* VI);
+double qto_kinetic_energy(const qto_physics* p, int32_t k);
 
 #ifdef __cplusplus
 }

@@ -509,3 +509,83 @@ def test_ksu_width_decay_closed_form(oracle_lib):
     u /= np.sqrt(dr * np.sum(u ** 2))
     expect = dr * np.sum(u ** 2 * np.exp(2 * steps * dt * VI))   # |exp(dt V_I / 2)|^2 twice a step
     assert abs(out["norm"][0] - expect) < 1e-10
+
+
+# ------------------------------------------------ vacuum eigenstates (basis)
+
+def test_eigen_basis_free_particle_is_the_sine_modes(oracle_lib):
+    """Without the Coulomb term an S state sees no potential: the l = 0
+    states are the sine modes k = 1, 2, 3 of the box, normalised, with the
+    mode energies E_k of either kinetic operator (Sec. "Derivative types")."""
+    for deriv in (0, 1):
+        cfg = W.base(N=256, L=20.0, alpha_s=0.0, deriv_type=deriv)
+        E, B = oracle.eigen_basis(cfg)
+        N, L, M = 256, 20.0, cfg["mass"]
+        dr = L / N
+        m = np.arange(N)
+        for b, k in ((0, 1), (1, 2), (3, 3)):
+            p = np.pi * k / L
+            Ek = p * p / M if deriv == 0 else 2 * (1 - np.cos(p * dr)) / (M * dr * dr)
+            assert abs(E[b] - Ek) <= 1e-10 * Ek
+            u = np.sqrt(2.0 / L) * np.sin(np.pi * k * m / N)
+            np.testing.assert_allclose(B[b], u, atol=1e-10)
+
+
+def test_eigen_basis_coulomb_levels_converge_to_bohr(oracle_lib):
+    """Coulomb potential -C_F alpha_s / r: the levels approach the Bohr levels
+    -M (C_F alpha_s)^2 / (4 n^2) (reduced mass M/2); the S states, whose
+    wave function has a cusp at the origin, carry the grid's O(dr^2) error,
+    which quarters when dr halves."""
+    alpha = 4.0 / 3.0 * 0.3
+    errs = {}
+    for N in (512, 1024):
+        cfg = W.base(N=N, L=40.0, alpha_s=0.3)
+        E, B = oracle.eigen_basis(cfg)
+        M = cfg["mass"]
+        rel = [E[b] / (-M * alpha * alpha / (4 * n * n)) - 1.0
+               for b, n in enumerate((1, 2, 2, 3, 3, 3))]
+        errs[N] = rel
+        assert max(abs(x) for x in rel) < 4e-3
+        for b in (2, 4, 5):                      # P and D states
+            assert abs(rel[b]) < 2e-4
+        # the analytic Coulomb states: overlaps near 1
+        for b, (n, l) in enumerate(((1, 0), (2, 0), (2, 1), (3, 0), (3, 1), (3, 2))):
+            u = oracle.basis_state(N, 40.0, M, 0.3, n, l)
+            ov = (40.0 / N) * float(B[b] @ u)
+            assert ov > 0.999, (N, n, l, ov)
+    ratio = errs[512][0] / errs[1024][0]
+    assert 3.5 < ratio < 4.5, ratio
+
+
+def test_eigen_basis_ksu_ground_state_against_shooting(oracle_lib):
+    """KSU at T = 0 is the Cornell potential with string breaking: the grid
+    ground state agrees with the continuum 1S energy found by shooting the
+    radial equation -u''/M + V u = E u (u(0) = 0) with an adaptive ODE
+    integrator and bisection on E."""
+    from scipy.integrate import solve_ivp
+    cfg = W.base(N=1024, L=24.0, potential=W.POTENTIAL_KSU, alpha_s=0.3)
+    E, B = oracle.eigen_basis(cfg)
+    M = cfg["mass"]
+    a, sigma, rsb = 0.409, 0.21, 1.25 / 0.1973269804
+    vsb = -a / rsb + sigma * rsb
+
+    def V(r):
+        return min(-a / r + sigma * r, vsb)
+
+    def tail(e):
+        r0 = 1e-6
+        # series start u = r (1 - M a r / 2), the Coulomb cusp
+        y0 = [r0 * (1 - M * a * r0 / 2), 1 - M * a * r0]
+        sol = solve_ivp(lambda r, y: [y[1], M * (V(r) - e) * y[0]], (r0, 12.0), y0,
+                        rtol=1e-11, atol=1e-14, method="DOP853")
+        return sol.y[0, -1]
+    lo, hi = E[0] - 0.05, E[0] + 0.05
+    assert tail(lo) * tail(hi) < 0
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        if tail(lo) * tail(mid) <= 0:
+            hi = mid
+        else:
+            lo = mid
+    e_cont = 0.5 * (lo + hi)
+    assert abs(E[0] - e_cont) < 3e-3 * abs(e_cont), (E[0], e_cont)
