@@ -63,7 +63,8 @@ typedef enum {
     QT_EBUSY = 4,       /* resource in use                                    */
     QT_ETIMEOUT = 5,    /* qt_wait ran out of time                            */
     QT_ECANCELED = 6,   /* the request was cancelled                          */
-    QT_ENOTFOUND = 7    /* unknown request id                                 */
+    QT_ENOTFOUND = 7,   /* unknown request id                                 */
+    QT_ENOCONV = 8      /* an iterative solver did not converge               */
 } qt_status;
 
 typedef enum { QT_FP64 = 0, QT_FP32_BULK = 1 } qt_precision;
@@ -244,6 +245,24 @@ qt_status qt_last_kernel_ms(qt_context* ctx, double* ms, int64_t* launches);
  * (runs kernels on the context's device). */
 qt_status qt_plan(qt_context* ctx, int32_t N, int32_t precision, int32_t tune,
                   int32_t* threads_per_traj, int32_t* traj_per_cu);
+
+/* Vacuum eigenstates 1S, 2S, 1P, 3S, 2P, 1D of the discrete Hamiltonian
+ * (paper: Sec. "Using the built-in eigensolvers"; the states that initType
+ * 100 starts from and ProjType 1 projects on).  The Hamiltonian is the one
+ * the evolution integrates at T = 0 for a singlet: the kinetic energy of
+ * phys->deriv_type, diagonal in the sine modes of the grid r_m = m dr
+ * (dr = L/N, m = 1..N-1, u_0 = u_N = 0), plus the vacuum potential of
+ * phys->potential (Munich: -(4/3) alpha_s / r; KSU: the Cornell potential
+ * with string breaking) and l(l+1)/(M r^2).  Uses phys->N (256, 512, ...,
+ * 8192), L, mass, alpha_s, deriv_type and potential; the rest is ignored.
+ * Output (host memory, caller-owned): energies[6] in GeV (binding energies:
+ * the state's mass is 2 M + energy) and basis[6 * N], row s the state s as
+ * u_m, m = 0..N-1, normalised to dr sum u_m^2 = 1 with u_1 > 0.  Runs
+ * kernels on the context's device and returns when done.  QT_EINVAL for an
+ * unsupported N or non-positive L or mass; QT_ENOCONV if the iteration
+ * does not converge. */
+qt_status qt_eigen_basis(qt_context* ctx, const qt_physics* phys, double* energies,
+                         double* basis);
 
 const char* qt_last_error(void);
 const char* qt_version(void);

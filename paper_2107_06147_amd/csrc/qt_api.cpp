@@ -203,6 +203,16 @@ private:
 
 static const int kBasisN[6] = {1, 2, 2, 3, 3, 3}, kBasisL[6] = {0, 0, 1, 0, 1, 2};
 
+// kinetic energy of sine mode k (Sec. "Derivative types"): p_k^2 / M, or
+// 2 (1 - cos(p_k dr)) / (M dr^2) for derivType 1, p_k = pi k / L
+double kinetic_energy(const qt_physics* p, int k)
+{
+    const double dr = p->L / p->N;
+    const double pk = kPi * k / p->L;
+    return p->deriv_type == 1 ? 2.0 * (1.0 - std::cos(pk * dr)) / (p->mass * dr * dr)
+                              : pk * pk / p->mass;
+}
+
 // kinetic factors (2/N) exp(-i E_k dt); 2/N is the scale of two
 // unnormalised sine transforms
 static std::shared_ptr<const std::vector<double>> kinetic_table(const qt_physics* p)
@@ -217,9 +227,7 @@ static std::shared_ptr<const std::vector<double>> kinetic_table(const qt_physics
         for (int k = 1; k < N; ++k) {
             double re = 1.0, im = 0.0;
             if (!off) {
-                const double pk = kPi * k / p->L;
-                const double E = p->deriv_type == 1 ? 2.0 * (1.0 - std::cos(pk * dr)) / (p->mass * dr * dr)
-                                                    : pk * pk / p->mass;
+                const double E = kinetic_energy(p, k);
                 re = std::cos(E * p->dt);
                 im = -std::sin(E * p->dt);
             }

@@ -41,6 +41,10 @@ qt_status fail(qt_status s, const char* fmt, ...);
     } while (0)
 
 int elem_bytes(int prec);     // bytes of one complex value of the precision
+double kinetic_energy(const qt_physics* p, int k);   // of sine mode k
+// vacuum eigenstates 1S, 2S, 1P, 3S, 2P, 1D (qt_eigen.cpp): energies [6],
+// basis [6 N] (host memory)
+qt_status eigen_basis(qt_context* ctx, const qt_physics* p, double* energies, double* basis);
 
 // Initial state (2N, normalised) and its overlaps with the six Coulomb
 // states.

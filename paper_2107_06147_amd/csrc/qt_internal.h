@@ -98,5 +98,9 @@ hipError_t plain_kinetic(const PlainArgs& a, hipStream_t s);
 hipError_t plain_norm_jump(const PlainArgs& a, int64_t n, hipStream_t s);
 hipError_t plain_finalize(const PlainArgs& a, hipStream_t s);
 bool plain_supported(int N);
+// y = S (f .* (S x)) + d .* x for n_vec real vectors of length N (rows of x
+// and y, device memory; d may be null), S the FP64 DST-I (qt_eigen.hip)
+hipError_t eig_apply(int N, const double* x, double* y, int n_vec, const double* f,
+                     const double* d, const void* tw, const void* prew, hipStream_t s);
 
 }  // namespace qt

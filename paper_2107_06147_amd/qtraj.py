@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqtraj.so")
 
-QT_OK, QT_EINVAL, QT_ENOMEM, QT_EDEVICE, QT_EBUSY, QT_ETIMEOUT, QT_ECANCELED, QT_ENOTFOUND = range(8)
+QT_OK, QT_EINVAL, QT_ENOMEM, QT_EDEVICE, QT_EBUSY, QT_ETIMEOUT, QT_ECANCELED, QT_ENOTFOUND, QT_ENOCONV = range(9)
 QT_FP64, QT_FP32_BULK = 0, 1
 QT_FORM_FUSED, QT_FORM_PLAIN = 0, 1
 QT_INIT_COULOMB, QT_INIT_GAUSSIAN, QT_INIT_ARRAY = 0, 1, 2
@@ -105,6 +105,7 @@ _SIGS = {
     "qt_server_destroy": (C.c_int, [_VP]),
     "qt_last_kernel_ms": (C.c_int, [_VP, _D, _I64]),
     "qt_plan": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _I32, _I32]),
+    "qt_eigen_basis": (C.c_int, [_VP, C.POINTER(qt_physics), _D, _D]),
     "qt_last_error": (C.c_char_p, []),
     "qt_version": (C.c_char_p, []),
 }
@@ -285,6 +286,18 @@ class Context:
         check(lib().qt_plan(self.h, int(N), int(precision), int(bool(tune)), C.byref(w),
                             C.byref(s)), "qt_plan")
         return w.value, s.value
+
+
+def eigen_basis(ctx, cfg):
+    """Vacuum eigenstates 1S, 2S, 1P, 3S, 2P, 1D of the discrete Hamiltonian
+    (qt_eigen_basis): (energies [6] in GeV, basis [6, N])."""
+    N = int(cfg["N"])
+    e = np.zeros(6)
+    b = np.zeros((6, N))
+    p = physics(cfg)
+    check(lib().qt_eigen_basis(ctx.h, C.byref(p), e.ctypes.data_as(_D), b.ctypes.data_as(_D)),
+          "qt_eigen_basis")
+    return e, b
 
 
 def _stream_handle(stream):

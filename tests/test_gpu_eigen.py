@@ -1,0 +1,64 @@
+"""The library's vacuum eigensolver (qt_eigen_basis, Sec. "Using the
+built-in eigensolvers") against the oracle's dense diagonalisation of the
+same discrete Hamiltonian.  Marked `gpu`.
+
+Tolerance: the iteration stops when every wanted residual |H u - E u| is
+below 1e-13 times the largest entry scale of H (the largest mode energy
+plus the largest |V|, ~1e3 GeV at N = 512): energies then agree to ~1e-10
+relative and states, to the residual over the gap to the next level
+(>= 0.1 GeV), to ~1e-8; bounds 1e-9 and 1e-7."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_06147_amd import qtraj as qt
+from paper_2107_06147_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = qt.Context(0)
+    yield c
+    c.close()
+
+
+def _compare(cfg, e_gpu, b_gpu):
+    e_ref, b_ref = oracle.eigen_basis(cfg)
+    dr = cfg["L"] / cfg["N"]
+    de = np.max(np.abs(e_gpu - e_ref) / np.maximum(np.abs(e_ref), 1e-3))
+    du = max(np.sqrt(dr * np.sum((b_gpu[s] - b_ref[s]) ** 2)) for s in range(6))
+    return de, du
+
+
+@pytest.mark.parametrize("case", ["munich_512", "munich_512_deriv1", "ksu_512", "munich_2048"])
+def test_eigen_basis_against_oracle(ctx, case):
+    cfg = {
+        "munich_512": W.base(N=512, L=40.0, alpha_s=0.3),
+        "munich_512_deriv1": W.base(N=512, L=40.0, alpha_s=0.3, deriv_type=1),
+        "ksu_512": W.base(N=512, L=24.0, potential=W.POTENTIAL_KSU),
+        "munich_2048": W.base(N=2048, L=40.0, alpha_s=0.3),
+    }[case]
+    e, b = qt.eigen_basis(ctx, cfg)
+    de, du = _compare(cfg, e, b)
+    print("eigen", case, "energies", e, "dE", de, "du", du)
+    assert de <= 1e-9 and du <= 1e-7
+
+
+def test_eigen_basis_free_particle_exact(ctx):
+    """Without a potential the S states are the box's sine modes."""
+    cfg = W.base(N=256, L=20.0, alpha_s=0.0)
+    e, b = qt.eigen_basis(ctx, cfg)
+    N, L, M = 256, 20.0, cfg["mass"]
+    m = np.arange(N)
+    for s, k in ((0, 1), (1, 2), (3, 3)):
+        assert abs(e[s] - (np.pi * k / L) ** 2 / M) <= 1e-9 * e[s]
+        np.testing.assert_allclose(b[s], np.sqrt(2.0 / L) * np.sin(np.pi * k * m / N), atol=1e-8)
+
+
+def test_eigen_basis_rejects_bad_input(ctx):
+    with pytest.raises(qt.QtError):
+        qt.eigen_basis(ctx, W.base(N=300, L=20.0))
+    with pytest.raises(qt.QtError):
+        qt.eigen_basis(ctx, W.base(N=256, L=-1.0))
