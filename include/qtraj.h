@@ -34,11 +34,14 @@
  *            threshold (word 2); u = ((w >> 12) + 0.5) 2^-52.
  *   jump     iff norm <= threshold; l -> l-1 iff u_l < l/(2l+1), else l+1;
  *            octet -> singlet iff u_c < 2/7, singlet -> octet always.
- *   results  overlaps with the six Coulomb states 1S,2S,1P,3S,2P,1D (Bohr
- *            radius 2/(M alpha), normalised on the grid) of the final
+ *   results  overlaps with the six states 1S,2S,1P,3S,2P,1D of the
+ *            projection basis (phys->basis: the Coulomb states of Bohr
+ *            radius 2/(M alpha), or the vacuum eigenstates of
+ *            qt_eigen_basis), normalised on the grid, of the final
  *            normalised state, non-zero only for a singlet of matching l;
  *            survival = overlap / initial overlap (raw overlap where the
- *            initial overlap is 0).
+ *            initial overlap is below 1e-12: a state the initial state
+ *            does not populate).
  *
  * Threading: a context may be used from one host thread at a time; distinct
  * contexts are independent.  A server (qt_server_*) is thread-safe.
@@ -71,7 +74,11 @@ typedef enum { QT_FP64 = 0, QT_FP32_BULK = 1 } qt_precision;
 /* FUSED: one persistent kernel, state in registers/LDS for the whole run.
  * PLAIN: one kernel per sub-step per time step, state in HBM (FP64 only). */
 typedef enum { QT_FORM_FUSED = 0, QT_FORM_PLAIN = 1 } qt_form;
-typedef enum { QT_INIT_COULOMB = 0, QT_INIT_GAUSSIAN = 1, QT_INIT_ARRAY = 2 } qt_init_kind;
+typedef enum { QT_INIT_COULOMB = 0, QT_INIT_GAUSSIAN = 1, QT_INIT_ARRAY = 2, QT_INIT_EIGEN = 3 } qt_init_kind;
+
+/* Projection basis of the overlaps and survival probabilities (paper:
+ * ProjType 0 and 1). */
+typedef enum { QT_BASIS_COULOMB = 0, QT_BASIS_EIGEN = 1 } qt_basis_kind;
 typedef enum { QT_SINGLET = 0, QT_OCTET = 1 } qt_color;
 /* LMAX: l exceeded the tabulated range (l > 255; ends like MAXJUMPS).
  * NOJUMP: the first threshold lies below every norm of the batch's no-jump
@@ -106,6 +113,11 @@ typedef struct {
     int32_t flags;
     int32_t potential;     /* qt_potential */
     double  md_factor;     /* KSU: > 0 */
+    int32_t basis;         /* qt_basis_kind: the states the overlaps project on,
+                              the analytic Coulomb states or the vacuum
+                              eigenstates of qt_eigen_basis (computed on the
+                              device at the first use, cached per context) */
+    int32_t pad0;
 } qt_physics;
 
 /* Temperature table (paper: Temperature parameters).  Host pointers, read
@@ -127,8 +139,10 @@ typedef struct {
 
 /* Initial state (paper: Initial condition parameters).  COULOMB: hydrogen-
  * like (n, l) for n <= 3; GAUSSIAN: r^{l+1} exp(-r^2/(2 width^2)); ARRAY:
- * u_re/u_im host arrays of N values indexed by j (u_im may be NULL).  Every
- * initial state is normalised on the grid. */
+ * u_re/u_im host arrays of N values indexed by j (u_im may be NULL); EIGEN
+ * (paper: initType 100): the vacuum eigenstate (n, l) of qt_eigen_basis,
+ * one of 1S, 2S, 1P (n=2), 3S, 2P (n=3), 1D (n=3), singlet.  Every initial
+ * state is normalised on the grid. */
 typedef struct {
     int32_t kind, n, l, color;
     double  width;

@@ -22,7 +22,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 SINGLET, OCTET = 0, 1
-INIT_COULOMB, INIT_GAUSSIAN, INIT_ARRAY = 0, 1, 2
+INIT_COULOMB, INIT_GAUSSIAN, INIT_ARRAY, INIT_EIGEN = 0, 1, 2, 3
+BASIS_COULOMB, BASIS_EIGEN = 0, 1
 STATUS_OK, STATUS_RMAX, STATUS_MAXJUMPS, STATUS_NOJUMP = 0, 1, 2, 4
 POTENTIAL_MUNICH, POTENTIAL_KSU = 0, 1
 FLAG_KINETIC_OFF = 1
@@ -46,7 +47,8 @@ class _Physics(C.Structure):
                 ("kappa_hat", C.c_double), ("gamma_hat", C.c_double),
                 ("deriv_type", C.c_int32), ("do_jumps", C.c_int32),
                 ("max_jumps", C.c_int32), ("r_max", C.c_double),
-                ("flags", C.c_int32), ("potential", C.c_int32), ("md_factor", C.c_double)]
+                ("flags", C.c_int32), ("potential", C.c_int32), ("md_factor", C.c_double),
+                ("basis", C.POINTER(C.c_double))]
 
 
 class _TTable(C.Structure):
@@ -124,13 +126,13 @@ def _dptr(a):
     return None if a is None else a.ctypes.data_as(_D)
 
 
-def _physics(cfg):
+def _physics(cfg, basis=None):
     return _Physics(int(cfg["N"]), float(cfg["L"]), float(cfg["dt"]), float(cfg["mass"]),
                     float(cfg["alpha_s"]), float(cfg["kappa_hat"]), float(cfg["gamma_hat"]),
                     int(cfg.get("deriv_type", 0)), int(cfg.get("do_jumps", 1)),
                     int(cfg.get("max_jumps", -1)), float(cfg.get("r_max", 1.0)),
                     int(cfg.get("flags", 0)), int(cfg.get("potential", 0)),
-                    float(cfg.get("md_factor", 1.0)))
+                    float(cfg.get("md_factor", 1.0)), _dptr(basis))
 
 
 def _ttable(cfg, keep):
@@ -168,7 +170,19 @@ def run(cfg, n_traj=None, traj_id0=None, want_psi=False, want_trace=False,
     keep = []
     n = int(cfg["n_traj"] if n_traj is None else n_traj)
     t0 = int(cfg.get("traj_id0", 0) if traj_id0 is None else traj_id0)
-    p = _physics(cfg)
+    basis = None
+    if int(cfg.get("basis", BASIS_COULOMB)) == BASIS_EIGEN or \
+            int(cfg.get("init_kind", INIT_COULOMB)) == INIT_EIGEN:
+        _, eig = eigen_basis(cfg)
+        if int(cfg.get("basis", BASIS_COULOMB)) == BASIS_EIGEN:
+            basis = np.ascontiguousarray(eig)
+            keep.append(basis)
+        if int(cfg.get("init_kind", INIT_COULOMB)) == INIT_EIGEN:
+            # initType 100: the eigenstate (n, l) as an array initial state
+            slot = [(1, 0), (2, 0), (2, 1), (3, 0), (3, 1), (3, 2)].index(
+                (int(cfg.get("init_n", 1)), int(cfg.get("init_l", 0))))
+            cfg = dict(cfg, init_kind=INIT_ARRAY, u0=eig[slot].astype(complex))
+    p = _physics(cfg, basis)
     tt = _ttable(cfg, keep)
     ini = _init(cfg, keep)
     b = _Batch(n, int(cfg.get("seed", 1)), t0, int(cfg.get("traj_id_stride", 1)),
@@ -268,6 +282,9 @@ def potential(cfg, r, l, color=SINGLET, T=0.0):
     return vr.value, vi.value
 
 
+_EIGEN_CACHE = {}
+
+
 def eigen_basis(cfg):
     """Vacuum eigenstates 1S, 2S, 1P, 3S, 2P, 1D (Sec. "Using the built-in
     eigensolvers"): the eigenvectors of the discrete Hamiltonian that the
@@ -278,6 +295,11 @@ def eigen_basis(cfg):
     FP64 matrix and diagonalised (numpy.linalg.eigh); state n_r of angular
     momentum l is the (n_r + 1)-th lowest.  Each state is normalised to
     dr sum u_m^2 = 1 with u_1 > 0.  Returns (energies [6], basis [6, N])."""
+    key = (int(cfg["N"]), float(cfg["L"]), float(cfg["mass"]), float(cfg["alpha_s"]),
+           int(cfg.get("deriv_type", 0)), int(cfg.get("potential", 0)))
+    if key in _EIGEN_CACHE:
+        e, b = _EIGEN_CACHE[key]
+        return e.copy(), b.copy()
     N = int(cfg["N"])
     dr = float(cfg["L"]) / N
     p = _physics(cfg)
@@ -296,4 +318,5 @@ def eigen_basis(cfg):
                 u = -u
             energies[b] = w[nr]
             basis[b, 1:] = u
+    _EIGEN_CACHE[key] = (energies.copy(), basis.copy())
     return energies, basis

@@ -606,7 +606,10 @@ static void run_one(const shared_setup* s, int64_t i, workspace* w, int zeroth)
     if (status == QTO_STATUS_OK) {
         singlet_overlaps(N, dr, s->basis, l, c, w->re, w->im, ov);
         for (int bb = 0; bb < 6; ++bb)
-            sv[bb] = (s->init_overlap[bb] != 0.0) ? ov[bb] / s->init_overlap[bb] : ov[bb];
+            /* a state the initial state does not populate (population
+               below 1e-12: rounding) has no survival ratio; the overlap
+               itself is reported */
+            sv[bb] = (s->init_overlap[bb] > 1e-12) ? ov[bb] / s->init_overlap[bb] : ov[bb];
     }
     if (out->norm) out->norm[i] = norm;
     if (out->first_r) out->first_r[i] = first_r;
@@ -670,9 +673,12 @@ int qto_run(const qto_physics* p, const qto_ttable* tt, const qto_init* ini,
         mom_re[k] = cos(ph);
         mom_im[k] = sin(ph);
     }
-    /* without a Coulomb term there is no basis: overlaps are reported as 0 */
+    /* the given projection basis (ProjType 1), else the Coulomb states;
+       without a Coulomb term there is no Coulomb basis: overlaps are 0 */
     double* basis = (double*)calloc((size_t)6 * N, sizeof(double));
-    if (p->alpha_s > 0)
+    if (p->basis)
+        memcpy(basis, p->basis, sizeof(double) * 6 * (size_t)N);
+    else if (p->alpha_s > 0)
         for (int bb = 0; bb < 6; ++bb)
             qto_basis_state(N, p->L, p->mass, p->alpha_s, BASIS_N[bb], BASIS_L[bb], basis + (size_t)bb * N);
     double* init_re = (double*)calloc(N, sizeof(double));

@@ -49,6 +49,9 @@ typedef struct {
                              potential") or isotropic KSU (appendix
                              "Isotropic KSU potential"; singlet, no jumps)    */
     double  md_factor;    /* KSU: the Debye-mass factor F_mD                  */
+    const double* basis;  /* NULL: the Coulomb states; else 6 x N states to
+                             project on (ProjType 1: the vacuum eigenstates,
+                             see eigen_basis in __init__.py)                  */
 } qto_physics;
 
 typedef struct {

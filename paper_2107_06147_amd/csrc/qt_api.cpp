@@ -119,6 +119,11 @@ qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in, 
     case QT_INIT_ARRAY:
         if (!in->u_re) return fail(QT_EINVAL, "array initial state needs u_re");
         break;
+    case QT_INIT_EIGEN:
+        if (in->color != QT_SINGLET) return fail(QT_EINVAL, "eigenstate initial states are singlets");
+        if (!coulomb_state_known(in->n, in->l))
+            return fail(QT_EINVAL, "eigenstate (n=%d, l=%d) not computed (1S..1D)", in->n, in->l);
+        break;
     default: return fail(QT_EINVAL, "unknown initial state kind %d", in->kind);
     }
     if (b->n_traj < 0 || b->n_traj > 0x7fffffffLL) return fail(QT_EINVAL, "n_traj out of range");
@@ -131,6 +136,8 @@ qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in, 
     if (tt->vacuum_steps < 0) return fail(QT_EINVAL, "vacuum_steps must be >= 0");
     if (p->potential != QT_POTENTIAL_MUNICH && p->potential != QT_POTENTIAL_KSU)
         return fail(QT_EINVAL, "unknown potential %d", p->potential);
+    if (p->basis != QT_BASIS_COULOMB && p->basis != QT_BASIS_EIGEN)
+        return fail(QT_EINVAL, "unknown basis %d", p->basis);
     if (p->potential == QT_POTENTIAL_KSU) {
         if (p->do_jumps) return fail(QT_EINVAL, "the KSU potential runs without jumps");
         if (in->color != QT_SINGLET) return fail(QT_EINVAL, "the KSU potential is a singlet potential");
@@ -262,7 +269,8 @@ static std::shared_ptr<const std::vector<double>> basis_table(const qt_physics* 
 
 // Initial state and its overlaps; null if its norm is zero or not finite.
 static std::shared_ptr<const InitTable> make_init(const qt_physics* p, const qt_init* in,
-                                                  const std::vector<double>& basis)
+                                                  const std::vector<double>& basis,
+                                                  const std::vector<double>* eigen)
 {
     const int N = p->N;
     const double dr = p->L / N;
@@ -272,6 +280,10 @@ static std::shared_ptr<const InitTable> make_init(const qt_physics* p, const qt_
     if (in->kind == QT_INIT_COULOMB) {
         const double a0 = 2.0 / (p->mass * (4.0 / 3.0) * p->alpha_s);
         for (int j = 1; j < N; ++j) psi[2 * j] = hydrogen(in->n, in->l, a0, j * dr);
+    } else if (in->kind == QT_INIT_EIGEN) {
+        int q = 0;
+        while (kBasisN[q] != in->n || kBasisL[q] != in->l) ++q;
+        for (int j = 1; j < N; ++j) psi[2 * j] = (*eigen)[(size_t)q * N + j];
     } else if (in->kind == QT_INIT_GAUSSIAN) {
         for (int j = 1; j < N; ++j) {
             const double r = j * dr;
@@ -293,7 +305,8 @@ static std::shared_ptr<const InitTable> make_init(const qt_physics* p, const qt_
     for (int j = 1; j < N; ++j) nrm += psi[2 * j] * psi[2 * j] + psi[2 * j + 1] * psi[2 * j + 1];
     for (int q = 0; q < 6; ++q) {
         t->overlap[q] = 0.0;
-        if (in->color != QT_SINGLET || in->l != kBasisL[q] || !(p->alpha_s > 0)) continue;
+        if (in->color != QT_SINGLET || in->l != kBasisL[q]) continue;
+        if (p->basis == QT_BASIS_COULOMB && !(p->alpha_s > 0)) continue;
         double ar = 0.0, ai = 0.0;
         for (int j = 1; j < N; ++j) {
             ar += basis[(size_t)q * N + j] * psi[2 * j];
@@ -306,11 +319,18 @@ static std::shared_ptr<const InitTable> make_init(const qt_physics* p, const qt_
     return t;
 }
 
-qt_status prepare(const qt_physics* p, const qt_ttable* tt, const qt_init* in, const qt_batch* b,
-                  HostBatch* hb)
+qt_status prepare(qt_context* ctx, const qt_physics* p, const qt_ttable* tt, const qt_init* in,
+                  const qt_batch* b, HostBatch* hb)
 {
     qt_status st = validate(p, tt, in, b);
     if (st != QT_OK) return st;
+    // the vacuum eigenstates (ProjType 1, initType 100), computed on the
+    // device once per context and parameters
+    qt_context::Eigen eig;
+    if (p->basis == QT_BASIS_EIGEN || in->kind == QT_INIT_EIGEN) {
+        if (!ctx) return fail(QT_EINVAL, "eigenstates need a context");
+        if ((st = eigen_states(ctx, p, &eig)) != QT_OK) return st;
+    }
     hb->phys = *p;
     hb->batch = *b;
     hb->init_l = in->l;
@@ -322,14 +342,17 @@ qt_status prepare(const qt_physics* p, const qt_ttable* tt, const qt_init* in, c
     hb->n_steps = count_steps(*p, *tt);
     hb->vacuum_steps = tt->vacuum_steps;
     hb->kin = kinetic_table(p);
-    hb->basis = basis_table(p);
+    hb->basis = p->basis == QT_BASIS_EIGEN ? eig.basis : basis_table(p);
+    const std::vector<double>* ev = eig.basis ? eig.basis.get() : nullptr;
     if (in->kind == QT_INIT_ARRAY) {
-        hb->init = make_init(p, in, *hb->basis);
+        hb->init = make_init(p, in, *hb->basis, ev);
     } else {
         static TableCache<InitTable> cache;
         const std::vector<double> key{(double)p->N, p->L, p->mass, p->alpha_s, (double)in->kind,
-                                      (double)in->n, (double)in->l, (double)in->color, in->width};
-        hb->init = cache.get(key, [&] { return make_init(p, in, *hb->basis); });
+                                      (double)in->n, (double)in->l, (double)in->color, in->width,
+                                      (double)p->basis, (double)p->deriv_type,
+                                      (double)p->potential};
+        hb->init = cache.get(key, [&] { return make_init(p, in, *hb->basis, ev); });
     }
     if (!hb->init) return fail(QT_EINVAL, "initial state has zero or non-finite norm");
     return QT_OK;
@@ -927,7 +950,7 @@ qt_status tune_variant(qt_context* ctx, int prec, int N, qt_context::Variant* ou
     b.n_traj = (int64_t)ctx->n_cu * 8; b.seed = 12345; b.traj_id0 = 0; b.traj_id_stride = 1;
     b.precision = prec; b.form = QT_FORM_FUSED;
     HostBatch hb;
-    qt_status st = prepare(&p, &tt, &in, &b, &hb);
+    qt_status st = prepare(ctx, &p, &tt, &in, &b, &hb);
     if (st != QT_OK) return st;
     std::vector<const HostBatch*> v{&hb};
     std::vector<qt_results> outs(1);
@@ -1126,7 +1149,7 @@ qt_status qt_run(qt_context* ctx, const qt_physics* phys, const qt_ttable* tt, c
     std::lock_guard<std::mutex> lk(ctx->mu);
     QT_HIP(hipSetDevice(ctx->device));
     HostBatch hb;
-    qt_status st = prepare(phys, tt, init, batch, &hb);
+    qt_status st = prepare(ctx, phys, tt, init, batch, &hb);
     if (st != QT_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     std::vector<HostBatch*> hv{&hb};
@@ -1152,7 +1175,7 @@ qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys
     QT_HIP(hipSetDevice(ctx->device));
     std::vector<HostBatch> hbs(n_batches);
     for (int i = 0; i < n_batches; ++i) {
-        qt_status st = prepare(&phys[i], &tt[i], &init[i], &batch[i], &hbs[i]);
+        qt_status st = prepare(ctx, &phys[i], &tt[i], &init[i], &batch[i], &hbs[i]);
         if (st != QT_OK) return fail(st, "batch %d: %s", i, g_last_error.c_str());
         if (batch[i].form != QT_FORM_FUSED) return fail(QT_EINVAL, "batch %d: qt_run_many runs the fused form", i);
         if (batch[i].precision != batch[0].precision) return fail(QT_EINVAL, "batch %d: mixed precision", i);

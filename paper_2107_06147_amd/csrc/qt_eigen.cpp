@@ -23,6 +23,8 @@
 namespace qt {
 namespace {
 
+constexpr double kPiE = 3.14159265358979323846;
+
 // Cyclic Jacobi eigen-decomposition of the symmetric n x n matrix a
 // (row-major, destroyed): eigenvalues ascending in w, eigenvectors as the
 // columns of v (row-major).
@@ -144,8 +146,8 @@ struct Operator {
     double* dfh = nullptr;     // (2/N) E_k
     double* dfp = nullptr;     // (2/N) / (E_k + sigma)
     double* dv = nullptr;      // V_m (this l)
-    const void* tw = nullptr;
-    const void* prew = nullptr;
+    void* tw = nullptr;        // FFT twiddles and DST-I weights of length N
+    void* prew = nullptr;      // (its own: the context's caches are not locked here)
     int cap = 0;
     ~Operator()
     {
@@ -154,6 +156,8 @@ struct Operator {
         hipFree(dfh);
         hipFree(dfp);
         hipFree(dv);
+        hipFree(tw);
+        hipFree(prew);
     }
     qt_status apply(const std::vector<double>& x, int count, bool precond, std::vector<double>& y)
     {
@@ -295,7 +299,7 @@ qt_status lowest_states(Operator& op, const qt_physics* p, int l, int k, double*
 
 }  // namespace
 
-qt_status eigen_basis(qt_context* ctx, const qt_physics* p, double* energies, double* basis)
+static qt_status eigen_basis(const qt_physics* p, double* energies, double* basis)
 {
     const int N = p->N;
     if (!plain_supported(N)) return fail(QT_EINVAL, "N=%d not supported by the eigensolver", N);
@@ -303,14 +307,24 @@ qt_status eigen_basis(qt_context* ctx, const qt_physics* p, double* energies, do
     if (p->deriv_type != 0 && p->deriv_type != 1) return fail(QT_EINVAL, "deriv_type must be 0 or 1");
     if (p->potential != QT_POTENTIAL_MUNICH && p->potential != QT_POTENTIAL_KSU)
         return fail(QT_EINVAL, "unknown potential %d", p->potential);
-    qt_context::Tables t;
-    qt_status st = ensure_tables(ctx, QT_FP64, N, &t);
-    if (st != QT_OK) return st;
+    qt_status st = QT_OK;
     Operator op;
     op.N = N;
     op.cap = 15;                 // [X; W; P] for l = 0: 3 x (3 + 2)
-    op.tw = t.tw;
-    op.prew = t.prew;
+    {
+        std::vector<double> tw(2 * (size_t)N), sn(2 * (size_t)N);
+        for (int m = 0; m < N; ++m) {
+            tw[2 * m] = std::cos(2.0 * kPiE * m / N);
+            tw[2 * m + 1] = -std::sin(2.0 * kPiE * m / N);
+            const double sm = std::sin(kPiE * m / N);
+            sn[2 * m] = 0.5 * (sm + 0.5);
+            sn[2 * m + 1] = 0.5 * (sm - 0.5);
+        }
+        QT_HIP(hipMalloc(&op.tw, tw.size() * 8));
+        QT_HIP(hipMalloc(&op.prew, sn.size() * 8));
+        QT_HIP(hipMemcpy(op.tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
+        QT_HIP(hipMemcpy(op.prew, sn.data(), sn.size() * 8, hipMemcpyHostToDevice));
+    }
     QT_HIP(hipStreamCreateWithFlags(&op.s, hipStreamNonBlocking));
     struct StreamGuard {
         hipStream_t s;
@@ -354,13 +368,37 @@ qt_status eigen_basis(qt_context* ctx, const qt_physics* p, double* energies, do
     return QT_OK;
 }
 
+qt_status eigen_states(qt_context* ctx, const qt_physics* p, qt_context::Eigen* out)
+{
+    const std::vector<double> key{(double)p->N, p->L, p->mass, p->alpha_s, (double)p->deriv_type,
+                                  (double)p->potential};
+    std::lock_guard<std::mutex> lk(ctx->eig_mu);
+    auto it = ctx->eigen.find(key);
+    if (it != ctx->eigen.end()) {
+        *out = it->second;
+        return QT_OK;
+    }
+    QT_HIP(hipSetDevice(ctx->device));
+    qt_context::Eigen e;
+    auto b = std::make_shared<std::vector<double>>(6 * (size_t)p->N, 0.0);
+    qt_status st = eigen_basis(p, e.energies, b->data());
+    if (st != QT_OK) return st;
+    e.basis = b;
+    ctx->eigen[key] = e;
+    *out = e;
+    return QT_OK;
+}
+
 }  // namespace qt
 
 extern "C" qt_status qt_eigen_basis(qt_context* ctx, const qt_physics* phys, double* energies,
                                     double* basis)
 {
     if (!ctx || !phys || !energies || !basis) return qt::fail(QT_EINVAL, "null argument");
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    QT_HIP(hipSetDevice(ctx->device));
-    return qt::eigen_basis(ctx, phys, energies, basis);
+    qt_context::Eigen e;
+    qt_status st = qt::eigen_states(ctx, phys, &e);
+    if (st != QT_OK) return st;
+    std::copy(e.energies, e.energies + 6, energies);
+    std::copy(e.basis->begin(), e.basis->end(), basis);
+    return QT_OK;
 }

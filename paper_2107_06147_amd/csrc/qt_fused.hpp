@@ -412,7 +412,8 @@ __device__ __forceinline__ void write_results(const GroupDesc& g, int64_t idx, c
                 l == basis_l[bb] && nrm > 0.0) {
                 const double dr_ = g.dr * x[2 * bb], di_ = g.dr * x[2 * bb + 1];
                 ov = (dr_ * dr_ + di_ * di_) / (g.dr * nrm);
-                sv = g.init_overlap[bb] != 0.0 ? ov / g.init_overlap[bb] : ov;
+                // (an initial population below 1e-12 is rounding: no ratio)
+                sv = g.init_overlap[bb] > 1e-12 ? ov / g.init_overlap[bb] : ov;
             }
             if (o.overlap) o.overlap[6 * idx + bb] = ov;
             if (o.survival) o.survival[6 * idx + bb] = sv;

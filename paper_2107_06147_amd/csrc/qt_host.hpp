@@ -28,6 +28,15 @@ struct qt_context {
     std::map<std::vector<double>, void*> phase;
     // (phi, phi') table of the KSU potential's imaginary part, per precision
     std::map<int, void*> ksu_phi;
+    // vacuum eigenstates (energies[6] then basis[6 N]) keyed by (N, L, mass,
+    // alpha_s, deriv_type, potential); their own lock: requests are
+    // prepared outside `mu` by the server
+    std::mutex eig_mu;
+    struct Eigen {
+        double energies[6];
+        std::shared_ptr<const std::vector<double>> basis;   // 6 N
+    };
+    std::map<std::vector<double>, Eigen> eigen;
 };
 
 namespace qt {
@@ -43,8 +52,8 @@ qt_status fail(qt_status s, const char* fmt, ...);
 int elem_bytes(int prec);     // bytes of one complex value of the precision
 double kinetic_energy(const qt_physics* p, int k);   // of sine mode k
 // vacuum eigenstates 1S, 2S, 1P, 3S, 2P, 1D (qt_eigen.cpp): energies [6],
-// basis [6 N] (host memory)
-qt_status eigen_basis(qt_context* ctx, const qt_physics* p, double* energies, double* basis);
+// basis [6 N] (host memory); computed once per context and parameters
+qt_status eigen_states(qt_context* ctx, const qt_physics* p, qt_context::Eigen* out);
 
 // Initial state (2N, normalised) and its overlaps with the six Coulomb
 // states.
@@ -73,7 +82,7 @@ struct HostBatch {
 
 qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in,
                    const qt_batch* b);
-qt_status prepare(const qt_physics* p, const qt_ttable* tt, const qt_init* in,
+qt_status prepare(qt_context* ctx, const qt_physics* p, const qt_ttable* tt, const qt_init* in,
                   const qt_batch* b, HostBatch* out);
 int64_t count_steps(const qt_physics& p, const qt_ttable& tt);
 double host_temperature(const double* tau, const double* T, int n, double t);

@@ -105,7 +105,7 @@ qt_status qt_job_create(qt_context* ctx, const qt_physics* phys, const qt_ttable
     QT_HIP(hipSetDevice(ctx->device));
     auto* j = new qt_job();
     j->ctx = ctx;
-    qt_status st = prepare(phys, tt, init, batch, &j->hb);
+    qt_status st = prepare(ctx, phys, tt, init, batch, &j->hb);
     if (st == QT_OK && batch->form != QT_FORM_FUSED) st = fail(QT_EINVAL, "jobs run the fused form");
     if (st == QT_OK && batch->no_jump_shortcut)
         st = fail(QT_EINVAL, "the no-jump shortcut is not available in segmented jobs");

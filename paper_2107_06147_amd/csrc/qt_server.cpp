@@ -364,7 +364,7 @@ qt_status qt_submit(qt_server* s, const qt_physics* phys, const qt_ttable* tt, c
 {
     if (!s || !request_id) return fail(QT_EINVAL, "null argument");
     auto q = std::make_shared<Request>();
-    qt_status st = prepare(phys, tt, init, batch, &q->hb);
+    qt_status st = prepare(s->ctx, phys, tt, init, batch, &q->hb);
     if (st != QT_OK) return st;
     if (batch->no_jump_shortcut) return fail(QT_EINVAL, "the no-jump shortcut is not available in the server");
     if (batch->precision != s->cfg.precision) return fail(QT_EINVAL, "request precision differs from the server's");

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libqtraj.so")
 QT_OK, QT_EINVAL, QT_ENOMEM, QT_EDEVICE, QT_EBUSY, QT_ETIMEOUT, QT_ECANCELED, QT_ENOTFOUND, QT_ENOCONV = range(9)
 QT_FP64, QT_FP32_BULK = 0, 1
 QT_FORM_FUSED, QT_FORM_PLAIN = 0, 1
-QT_INIT_COULOMB, QT_INIT_GAUSSIAN, QT_INIT_ARRAY = 0, 1, 2
+QT_INIT_COULOMB, QT_INIT_GAUSSIAN, QT_INIT_ARRAY, QT_INIT_EIGEN = 0, 1, 2, 3
+QT_BASIS_COULOMB, QT_BASIS_EIGEN = 0, 1
 QT_SINGLET, QT_OCTET = 0, 1
 QT_TRAJ_OK, QT_TRAJ_RMAX, QT_TRAJ_MAXJUMPS, QT_TRAJ_LMAX, QT_TRAJ_NOJUMP = 0, 1, 2, 3, 4
 QT_POTENTIAL_MUNICH, QT_POTENTIAL_KSU = 0, 1
@@ -38,7 +39,7 @@ class qt_physics(C.Structure):
                 ("alpha_s", C.c_double), ("kappa_hat", C.c_double), ("gamma_hat", C.c_double),
                 ("deriv_type", C.c_int32), ("do_jumps", C.c_int32), ("max_jumps", C.c_int32),
                 ("r_max", C.c_double), ("flags", C.c_int32), ("potential", C.c_int32),
-                ("md_factor", C.c_double)]
+                ("md_factor", C.c_double), ("basis", C.c_int32), ("pad0", C.c_int32)]
 
 
 class qt_ttable(C.Structure):
@@ -154,7 +155,7 @@ def physics(cfg):
                       int(cfg.get("deriv_type", 0)), int(cfg.get("do_jumps", 1)),
                       int(cfg.get("max_jumps", -1)), float(cfg.get("r_max", 1.0)),
                       int(cfg.get("flags", 0)), int(cfg.get("potential", 0)),
-                      float(cfg.get("md_factor", 1.0)))
+                      float(cfg.get("md_factor", 1.0)), int(cfg.get("basis", 0)), 0)
 
 
 def ttable(cfg, keep):

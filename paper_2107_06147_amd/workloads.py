@@ -29,13 +29,14 @@ ALPHA_S = 0.3
 
 SINGLET, OCTET = 0, 1
 POTENTIAL_MUNICH, POTENTIAL_KSU = 0, 1
-INIT_COULOMB, INIT_GAUSSIAN, INIT_ARRAY = 0, 1, 2
+INIT_COULOMB, INIT_GAUSSIAN, INIT_ARRAY, INIT_EIGEN = 0, 1, 2, 3
+BASIS_COULOMB, BASIS_EIGEN = 0, 1
 
 
 def base(**kw):
     cfg = dict(N=512, L=40.0, dt=0.001, mass=MASS_B, alpha_s=ALPHA_S, kappa_hat=4.0,
                gamma_hat=0.0, deriv_type=0, do_jumps=1, max_jumps=-1, r_max=1.0, flags=0,
-               potential=0, md_factor=1.0,
+               potential=0, md_factor=1.0, basis=0,
                tau=np.array([0.0, 1.0e9]), T=np.array([0.4, 0.4]), tau_start=0.0,
                T_final=0.0, max_steps=1000, vacuum_steps=0,
                init_kind=INIT_COULOMB, init_n=1, init_l=0, init_color=SINGLET, init_width=0.0,

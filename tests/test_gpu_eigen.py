@@ -62,3 +62,34 @@ def test_eigen_basis_rejects_bad_input(ctx):
         qt.eigen_basis(ctx, W.base(N=300, L=20.0))
     with pytest.raises(qt.QtError):
         qt.eigen_basis(ctx, W.base(N=256, L=-1.0))
+
+
+F64, F32 = qt.QT_FP64, qt.QT_FP32_BULK
+FUSED, PLAIN = qt.QT_FORM_FUSED, qt.QT_FORM_PLAIN
+
+
+@pytest.mark.parametrize("prec,form", [(F64, FUSED), (F64, PLAIN), (F32, FUSED)])
+def test_run_from_eigenstates_projected_on_them(ctx, prec, form):
+    """initType 100 and ProjType 1: trajectories start from the computed 1S
+    (and 1P) and report overlaps with the computed states; every trajectory
+    matches the oracle, which uses its own dense eigenstates."""
+    from tests.gpu_parity import compare, gpu_run
+    for n, l in ((1, 0), (2, 1)):
+        cfg = W.base(N=512, L=20.0, dt=0.001, kappa_hat=4.0, n_traj=10, seed=31,
+                     init_kind=W.INIT_EIGEN, init_n=n, init_l=l, basis=W.BASIS_EIGEN,
+                     **W.constant_T(0.4, 400))
+        ref = oracle.run(cfg, want_psi=True)
+        out = gpu_run(ctx, cfg, prec, form=form)
+        print("eigen run", prec, form, n, l, compare(ref, out, prec, label="eigen run"),
+              "jumps", int(ref["n_jumps"].sum()))
+
+
+def test_eigenstate_is_nearly_stationary(ctx):
+    """In vacuum without jumps the computed 1S keeps its overlap with itself
+    (the Strang step is exact to O(dt^3) per step)."""
+    from tests.gpu_parity import gpu_run
+    cfg = W.base(N=512, L=20.0, dt=0.001, kappa_hat=0.0, do_jumps=0, n_traj=2,
+                 init_kind=W.INIT_EIGEN, init_n=1, init_l=0, basis=W.BASIS_EIGEN,
+                 **W.constant_T(0.0, 500))
+    out = gpu_run(ctx, cfg, F64)
+    assert abs(out["overlap"][0][0] - 1.0) < 1e-6, out["overlap"][0]
