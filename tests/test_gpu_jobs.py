@@ -170,3 +170,32 @@ def test_server_rejects_bad_requests_and_keeps_running(ctx):
         srv.wait(rid2, timeout_s=120)
     assert e.value.status == qt.QT_ECANCELED
     srv.close()
+
+
+def test_eigen_basis_and_ksu_through_jobs_and_server(ctx):
+    """Segmented jobs and the server reproduce single runs bitwise for the
+    computed eigenstate basis (initType 100 with ProjType 1) and for the
+    KSU potential."""
+    import torch
+    tau, T = W.bjorken_table(0.5, 0.6, 0.25, 200)
+    eig = W.base(N=512, L=20.0, dt=0.001, kappa_hat=4.0, n_traj=12, seed=41,
+                 init_kind=W.INIT_EIGEN, init_n=1, init_l=0, basis=W.BASIS_EIGEN,
+                 **W.constant_T(0.45, 250))
+    ksu = W.base(N=512, L=20.0, dt=0.002, potential=W.POTENTIAL_KSU, do_jumps=0,
+                 kappa_hat=0.0, n_traj=6, seed=42, tau=tau, T=T, tau_start=float(tau[0]),
+                 T_final=0.25, max_steps=250)
+    for cfg in (eig, ksu):
+        ref = gpu_run(ctx, cfg, F32)
+        job = qt.Job(ctx, cfg, precision=F32, segment_steps=40)
+        job.advance(250)
+        assert job.done()
+        out = qt.to_numpy(job.results(want_psi=True))
+        torch.cuda.synchronize()
+        job.close()
+        _same(ref, out)
+    srv = qt.Server(ctx, precision=F32, segment_steps=64)
+    ids = [srv.submit(c) for c in (eig, ksu)]
+    outs = [srv.wait(i, timeout_s=120, want_psi=True) for i in ids]
+    srv.close()
+    for c, o in zip((eig, ksu), outs):
+        _same(gpu_run(ctx, c, F32), o)
