@@ -84,24 +84,13 @@ __device__ __forceinline__ cx<R> ldg(const cx<R>* p, uint32_t i)
     z.im = v.y;
     return z;
 }
-// Kinetic factor of one momentum: FP32-bulk keeps it as a double-float
-// (hi + lo, both FP32) in one 16-byte element; FP64 as one complex.
-template <class R> struct Kin;
-template <> struct Kin<float> { cx<float> hi, lo; };
-template <> struct Kin<double> { cx<double> v; };
-__device__ __forceinline__ Kin<float> ldg(const Kin<float>* p, uint32_t i)
+// Kinetic factor of one momentum (one complex value).
+template <class R> struct Kin { cx<R> v; };
+template <class R>
+__device__ __forceinline__ Kin<R> ldg(const Kin<R>* p, uint32_t i)
 {
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    const v4 v = *(const QT_GLOBAL v4*)((const QT_GLOBAL char*)p + i * 16u);
-    Kin<float> k;
-    k.hi = mk(v.x, v.y);
-    k.lo = mk(v.z, v.w);
-    return k;
-}
-__device__ __forceinline__ Kin<double> ldg(const Kin<double>* p, uint32_t i)
-{
-    Kin<double> k;
-    k.v = ldg(reinterpret_cast<const cx<double>*>(p), i);
+    Kin<R> k;
+    k.v = ldg(reinterpret_cast<const cx<R>*>(p), i);
     return k;
 }
 template <class R>
@@ -585,11 +574,7 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const 
     const cx<R> off = block_exclusive_scan<W>(run, wsum) - scale(d0, R(0.5));
     sfor<0, CH>([&](auto I) QT_INL { chunk[padc<2 * I + 1>()] = pre[I] + off; });
     __syncthreads();
-    // F * kin (FP32: hi and lo parts of the double-float factor)
-    auto kmul = [&](cx<R> F, const Kin<R>& k) QT_INL {
-        if constexpr (std::is_same<R, float>::value) return F * k.hi + F * k.lo;
-        else return F * k.v;
-    };
+    auto kmul = [&](cx<R> F, const Kin<R>& k) QT_INL { return F * k.v; };
     {
         const cx<R>* sa = buf + pad(ln.ja);
         const cx<R>* sb = buf + pad(ln.jb);
