@@ -401,18 +401,25 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
     qt_context::Tables t;
     if (f32) {
         // the FP32 sine transform (split form, qt_dst32.hpp), one block:
-        // FP32 [FFT twiddles of length M = N/2 | exp(-i pi j/N), j < M],
-        // FP64 [FFT twiddles, DST-I weights of length M | the same of length N]
+        // FP32 [FFT twiddles of length M = N/2, rounding a | exp(-i pi j/N),
+        // j < M | FFT twiddles, rounding b], FP64 [FFT twiddles, DST-I
+        // weights of length M | the same of length N].  Rounding a is to
+        // nearest; b rounds 2w - a, so that (a + b)/2 lies closer to w than
+        // either.  The kernel alternates the two step by step: the rounding
+        // error of the twiddles, the same every step with one table, then
+        // largely cancels between consecutive steps instead of adding up.
+        // (The neighbour of modulus closest to 1 would trade the modulus
+        // error for a larger phase error, which adds up the same way.)
         const int M = N / 2;
-        // (each component rounded to nearest: choosing the neighbour of
-        // modulus closest to 1 instead trades the modulus error for a
-        // larger phase error, which the steps accumulate the same way)
-        std::vector<float> f(4 * (size_t)M);
+        std::vector<float> f(6 * (size_t)M);
         for (int m = 0; m < M; ++m) {
-            f[2 * m] = (float)std::cos(2.0 * kPi * m / M);
-            f[2 * m + 1] = (float)-std::sin(2.0 * kPi * m / M);
-            f[2 * (M + m)] = (float)std::cos(kPi * m / N);
-            f[2 * (M + m) + 1] = (float)-std::sin(kPi * m / N);
+            const double c = std::cos(2.0 * kPi * m / M), s = -std::sin(2.0 * kPi * m / M);
+            f[2 * m] = (float)c;
+            f[2 * m + 1] = (float)s;
+            f[2 * (2 * (size_t)M + m)] = (float)(2.0 * c - (double)f[2 * m]);
+            f[2 * (2 * (size_t)M + m) + 1] = (float)(2.0 * s - (double)f[2 * m + 1]);
+            f[2 * ((size_t)M + m)] = (float)std::cos(kPi * m / N);
+            f[2 * ((size_t)M + m) + 1] = (float)-std::sin(kPi * m / N);
         }
         std::vector<double> d(4 * (size_t)M + 4 * (size_t)N);
         fill(M, &d[0], &d[2 * (size_t)M]);

@@ -31,9 +31,12 @@
 // transpose of the first (kin_block32), so neither leaves its slots.
 //
 // Tables (one block, see ensure_tables): FP32 [FFT twiddles of length M |
-// e^{-i pi j/N}, j < M], then FP64 [FFT twiddles of length M | DST-I weights
-// of length M | FFT twiddles of length N | DST-I weights of length N].  The
-// kinetic factors are in the slot order of kin_block32 (below).
+// e^{-i pi j/N}, j < M | the FFT twiddles in a second rounding], then FP64
+// [FFT twiddles of length M | DST-I weights of length M | FFT twiddles of
+// length N | DST-I weights of length N].  The two roundings of the FP32
+// twiddles alternate step by step: their error, otherwise the same every
+// step, then largely cancels between consecutive steps.  The kinetic factors
+// are in the slot order of kin_block32 (below).
 #pragma once
 #include "qt_device.hpp"
 
@@ -42,18 +45,19 @@ namespace qt {
 template <int N>
 struct Dst32Tables {
     static constexpr int M = N / 2;
-    const cx<float>* tw32;     // FFT twiddles, length M
+    const cx<float>* tw32;     // FFT twiddles, length M (rounding a or b)
     const cx<float>* wd;       // e^{-i pi j / N}, j < M
     const cx<double>* tw64h;   // FFT twiddles, length M
     const cx<double>* pre64h;  // DST-I weights, length M
     const cx<double>* tw64;    // FFT twiddles, length N
     const cx<double>* pre64;   // DST-I weights, length N
-    __device__ __forceinline__ explicit Dst32Tables(const void* base)
+    // the FP32 twiddles in rounding b when `second` (see ensure_tables)
+    __device__ __forceinline__ Dst32Tables(const void* base, bool second)
     {
         const char* p = static_cast<const char*>(base);
-        tw32 = reinterpret_cast<const cx<float>*>(p);
-        wd = tw32 + M;
-        tw64h = reinterpret_cast<const cx<double>*>(p + 2 * (size_t)M * sizeof(cx<float>));
+        tw32 = reinterpret_cast<const cx<float>*>(p) + (second ? 2 * M : 0);
+        wd = reinterpret_cast<const cx<float>*>(p) + M;
+        tw64h = reinterpret_cast<const cx<double>*>(p + 3 * (size_t)M * sizeof(cx<float>));
         pre64h = tw64h + M;
         tw64 = pre64h + M;
         pre64 = tw64 + N;
@@ -101,16 +105,16 @@ constexpr size_t dst32_buf_bytes()
 // is K_{2q}.
 // On entry a/b hold x in the mirror layout of length N, on exit the result
 // in the same layout.  buf: LDS of dst32_buf_bytes<N, W>(); wsum: W/64
-// cx<double> of LDS.
+// cx<double> of LDS; odd_step selects the FP32 twiddles' second rounding.
 template <int N, int W>
 __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const Lanes<N, W>& ln_in,
                                             void* buf, cx<double>* wsum, const void* tables,
-                                            const cx<double>* __restrict__ kin)
+                                            const cx<double>* __restrict__ kin, bool odd_step)
 {
     using PL = Plan<N, W>;
     constexpr int R1 = PL::R1, T = PL::T;
     constexpr int M = N / 2;
-    const Dst32Tables<N> tb(opaque(static_cast<const char*>(tables)));
+    const Dst32Tables<N> tb(opaque(static_cast<const char*>(tables)), odd_step);
     if constexpr (PL::P < 8) {
         // widened: dst1 of length N in FP64, the kinetic factors in between
         // (natural order from the slot-ordered table)

@@ -623,7 +623,8 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
                 });
             }
             if constexpr (kRenorm) {
-                kin_block32<N, W>(a, b, ls, buf, wsum, A.tw, static_cast<const cx<double>*>(g.kin));
+                kin_block32<N, W>(a, b, ls, buf, wsum, A.tw, static_cast<const cx<double>*>(g.kin),
+                                  (n & 1) != 0);
             } else {
                 const Kin<double>* kin = static_cast<const Kin<double>*>(g.kin);
                 cx<double> pw[Plan<N, W>::R1];
