@@ -275,25 +275,16 @@ struct PassTwiddles {
     }
 };
 
-// One Stockham pass: twiddle, butterfly, and (unless last) exchange through
-// LDS into the input layout of the next pass.  Butterfly j of a pass with
-// stride NS reads x[j + r N/RAD] and writes y[(j/NS) NS RAD + j%NS + r NS].
-// The next pass's twiddles are loaded before the exchange, so that their
-// latency overlaps it.
+// Butterflies of pass p: twiddle (passes after the first), then the DFT of
+// each of this lane's B groups of RAD values.
 template <class R, int N, int W, int p>
-__device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf,
-                                           const cx<R>* __restrict__ tw,
-                                           const PassTwiddles<R, N, W, p>& cur)
+__device__ __forceinline__ void fft_pass(cx<R>* v, const PassTwiddles<R, N, W, p>& cur)
 {
-    using PL = Plan<N, W>;
     using TW = PassTwiddles<R, N, W, p>;
     constexpr int RAD = TW::RAD;
-    constexpr int NS = TW::NS;
-    constexpr int B = TW::B;
-
-    sfor<0, B>([&](auto Q) QT_INL {
+    sfor<0, TW::B>([&](auto Q) QT_INL {
         constexpr int q = Q;
-        if constexpr (NS > 1) {
+        if constexpr (TW::NS > 1) {
             sfor<1, RAD>([&](auto Rr) QT_INL {
                 constexpr int r = Rr;
                 v[q * RAD + r] = v[q * RAD + r] * cur.w[q * (RAD - 1) + r - 1];
@@ -301,26 +292,84 @@ __device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R
         }
         dft<RAD>(v + q * RAD);
     });
-    if constexpr (p + 1 < PL::NPASS) {
+}
+
+// The exchange after pass p through LDS into the input layout of pass p + 1:
+// write, barrier, read.  Butterfly j of a pass with stride NS reads
+// x[j + r N/RAD] and writes y[(j/NS) NS RAD + j%NS + r NS].
+template <class R, int N, int W, int p>
+__device__ __forceinline__ void fft_exchange(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf)
+{
+    using PL = Plan<N, W>;
+    using TW = PassTwiddles<R, N, W, p>;
+    constexpr int RAD = TW::RAD;
+    constexpr int NS = TW::NS;
+    sfor<0, TW::B>([&](auto Q) QT_INL {
+        constexpr int q = Q;
+        const int j = TW::bfly(ln, q);
+        cx<R>* dst = buf + pad((j / NS) * NS * RAD + (j & (NS - 1)));
+        sfor<0, RAD>([&](auto Rr) QT_INL { dst[padc<Rr * NS>()] = v[q * RAD + Rr]; });
+    });
+    __syncthreads();
+    constexpr int RAD2 = PL::radix(p + 1);
+    constexpr int B2 = PL::P / RAD2;
+    sfor<0, B2>([&](auto Q) QT_INL {
+        constexpr int q = Q;
+        const int j = PassTwiddles<R, N, W, p + 1>::bfly(ln, q);
+        const cx<R>* src = buf + pad(j);
+        sfor<0, RAD2>([&](auto Rr) QT_INL { v[q * RAD2 + Rr] = src[padc<Rr * (N / RAD2)>()]; });
+    });
+}
+
+// The passes p.. of the FFT.  The next pass's twiddles are loaded before
+// the exchange, so that their latency overlaps it; a barrier follows each
+// exchange's read, so that the next exchange may overwrite the buffer.
+template <class R, int N, int W, int p>
+__device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf,
+                                           const cx<R>* __restrict__ tw,
+                                           const PassTwiddles<R, N, W, p>& cur)
+{
+    fft_pass<R, N, W, p>(v, cur);
+    if constexpr (p + 1 < Plan<N, W>::NPASS) {
         PassTwiddles<R, N, W, p + 1> nxt;
         nxt.load(ln, opaque(tw));
-        sfor<0, B>([&](auto Q) QT_INL {
-            constexpr int q = Q;
-            const int j = TW::bfly(ln, q);
-            cx<R>* dst = buf + pad((j / NS) * NS * RAD + (j & (NS - 1)));
-            sfor<0, RAD>([&](auto Rr) QT_INL { dst[padc<Rr * NS>()] = v[q * RAD + Rr]; });
-        });
-        __syncthreads();
-        constexpr int RAD2 = PL::radix(p + 1);
-        constexpr int B2 = PL::P / RAD2;
-        sfor<0, B2>([&](auto Q) QT_INL {
-            constexpr int q = Q;
-            const int j = PassTwiddles<R, N, W, p + 1>::bfly(ln, q);
-            const cx<R>* src = buf + pad(j);
-            sfor<0, RAD2>([&](auto Rr) QT_INL { v[q * RAD2 + Rr] = src[padc<Rr * (N / RAD2)>()]; });
-        });
+        fft_exchange<R, N, W, p>(v, ln, buf);
         __syncthreads();
         fft_passes<R, N, W, p + 1>(v, ln, buf, tw, nxt);
+    }
+}
+
+// The twiddles of every pass from p on, for FFTs that run more than once
+// with the same table and lanes.
+template <class R, int N, int W, int p, bool END = (p >= Plan<N, W>::NPASS)>
+struct AllTwiddles {
+    PassTwiddles<R, N, W, p> cur;
+    AllTwiddles<R, N, W, p + 1> rest;
+    __device__ __forceinline__ void load(const Lanes<N, W>& ln, const cx<R>* tw)
+    {
+        cur.load(ln, tw);
+        rest.load(ln, tw);
+    }
+};
+template <class R, int N, int W, int p>
+struct AllTwiddles<R, N, W, p, true> {
+    __device__ __forceinline__ void load(const Lanes<N, W>&, const cx<R>*) {}
+};
+
+// fft_passes with the twiddles already in registers, and two exchange
+// buffers: exchanges alternate between buf and buf2, with no barrier after
+// the read (a wave writes a buffer again only after the barrier of the
+// exchange in between, which every wave reaches after its reads of that
+// buffer).  The caller owes a barrier before it next writes the buffer of
+// the last exchange, or the other one before that.
+template <class R, int N, int W, int p>
+__device__ __forceinline__ void fft_passes_held(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf,
+                                                cx<R>* buf2, const AllTwiddles<R, N, W, p>& tws)
+{
+    fft_pass<R, N, W, p>(v, tws.cur);
+    if constexpr (p + 1 < Plan<N, W>::NPASS) {
+        fft_exchange<R, N, W, p>(v, ln, buf);
+        fft_passes_held<R, N, W, p + 1>(v, ln, buf2, buf, tws.rest);
     }
 }
 

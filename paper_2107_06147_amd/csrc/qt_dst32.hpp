@@ -81,6 +81,8 @@ __device__ __forceinline__ cx<float> mulk(cx<float> f, cx<double> k)
 
 // LDS bytes of the exchange buffer that the FP32 kinetic block of length N
 // on W lanes needs.
+// (With eight or more values per lane: the FP64 buffer of length N/2, which
+// also holds the two FP32 buffers of the cosine transform's FFTs.)
 template <int N, int W>
 constexpr size_t dst32_buf_bytes()
 {
@@ -198,11 +200,16 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
                 });
             }
         }
-        cx<float>* b32 = static_cast<cx<float>*>(buf);
-        {
-            PassTwiddles<float, M, W, 0> none;
-            fft_passes<float, M, W, 0>(v, ln, b32, opaque(tb.tw32), none);
-        }
+        // two exchange buffers (together the size of the FP64 one): the
+        // first FFT exchanges through X, Y, X, ..., the second starts with
+        // the other of the two that the first one ended on
+        cx<float>* const bx = static_cast<cx<float>*>(buf);
+        cx<float>* const by = bx + padded_len<M>();
+        constexpr int NX = PH::NPASS - 1;   // exchanges per FFT
+        // both FFTs take the same twiddles: loaded once
+        AllTwiddles<float, M, W, 0> tws;
+        tws.load(ln, opaque(tb.tw32));
+        fft_passes_held<float, M, W, 0>(v, ln, bx, by, tws);
         // slots n (v[r] at n = ja + rT, v[H + r] at jb + rT) times conj(K)/4
         {
             const cx<double>* kn = opaque(kin);
@@ -212,10 +219,12 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
                 v[H + r] = mulk(v[H + r], ldg(kn, (uint32_t)(ln.jb + r * T)));
             });
         }
-        {
-            PassTwiddles<float, M, W, 0> none;
-            fft_passes<float, M, W, 0>(v, ln, b32, opaque(tb.tw32), none);
-        }
+        if constexpr (NX % 2 == 1)
+            fft_passes_held<float, M, W, 0>(v, ln, by, bx, tws);
+        else
+            fft_passes_held<float, M, W, 0>(v, ln, bx, by, tws);
+        // the FP64 transforms below write the whole buffer
+        __syncthreads();
         // C^T: U = conj(v); a+'_j = i (e_j U_{M-j} - conj(e_j) U_j), e_j =
         // e^{-i pi j/N}; a+'_M = 2 U_0 (lane 0)
         {
