@@ -248,7 +248,13 @@ struct Lanes {
 };
 
 // Twiddle factors of pass p for this lane's butterflies (none for the first
-// pass, whose stride is 1).
+// pass, whose stride is 1): w^{r k}, r = 1..RAD-1, for butterfly k.  FP32
+// reads each from the table (its rounding is what limits the FP32 form's
+// accuracy).  FP64 reads w^k only and forms the other powers as products of
+// two lower ones, w^{r k} = w^{h k} w^{(r-h) k} with h the largest power of
+// two below r (r/2 for a power of two): at most three products deep, a few
+// units of the FP64 roundoff, and one table read where there were RAD - 1
+// (table reads, not arithmetic, are what the transforms wait for).
 template <class R, int N, int W, int p>
 struct PassTwiddles {
     using PL = Plan<N, W>;
@@ -267,9 +273,19 @@ struct PassTwiddles {
         if constexpr (NS > 1) {
             sfor<0, B>([&](auto Q) QT_INL {
                 const int k = bfly(ln, Q) & (NS - 1);
-                sfor<1, RAD>([&](auto Rr) QT_INL {
-                    w[Q * (RAD - 1) + Rr - 1] = ldg(tw, Rr * k * (N / (NS * RAD)));
-                });
+                cx<R>* wq = w + Q * (RAD - 1);   // wq[r - 1] = w^{r k}
+                if constexpr (sizeof(R) == sizeof(double)) {
+                    wq[0] = ldg(tw, k * (N / (NS * RAD)));
+                    sfor<2, RAD>([&](auto Rr) QT_INL {
+                        constexpr int r = Rr;
+                        constexpr int h = (r & (r - 1)) ? (1 << ilog2(r)) : r / 2;
+                        wq[r - 1] = wq[h - 1] * wq[r - h - 1];
+                    });
+                } else {
+                    sfor<1, RAD>([&](auto Rr) QT_INL {
+                        wq[Rr - 1] = ldg(tw, Rr * k * (N / (NS * RAD)));
+                    });
+                }
             });
         }
     }

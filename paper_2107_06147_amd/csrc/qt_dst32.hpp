@@ -180,25 +180,31 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
         // v[H + r] at j = jb + rT).  Lanes t > 0: the mirror M - j of ja + rT
         // is jb + (H-1-r) T and vice versa; lane 0: rT pairs with (H - r) T,
         // and V_0 = 2 a+_M.
-        cx<float> v[PH::P];
+        // e_j at this lane's slots (lane 0: ja = 0, jb = W), for C and C^T
+        cx<float> ea[H], eb[H];
         {
             const cx<float>* wd = opaque(tb.wd);
             sfor<0, H>([&](auto Rr) QT_INL {
-                constexpr int r = Rr;
-                v[r] = ldg(wd, ln.ja + r * T) * conj_plus_iconj(bp[H - 1 - r], ap[r]);
-                v[H + r] = ldg(wd, ln.jb + r * T) * conj_plus_iconj(ap[H - 1 - r], bp[r]);
+                ea[Rr] = ldg(wd, ln.ja + Rr * T);
+                eb[Rr] = ldg(wd, ln.jb + Rr * T);
             });
-            if (lane0) {
-                sfor<0, H>([&](auto Rr) QT_INL {
-                    constexpr int r = Rr;
-                    if constexpr (r == 0) {
-                        v[0] = mk(2.0f * apM.re, -2.0f * apM.im);
-                    } else {
-                        v[r] = ldg(wd, r * T) * conj_plus_iconj(ap[H - r], ap[r]);
-                    }
-                    v[H + r] = ldg(wd, W + r * T) * conj_plus_iconj(bp[H - 1 - r], bp[r]);
-                });
-            }
+        }
+        cx<float> v[PH::P];
+        sfor<0, H>([&](auto Rr) QT_INL {
+            constexpr int r = Rr;
+            v[r] = ea[r] * conj_plus_iconj(bp[H - 1 - r], ap[r]);
+            v[H + r] = eb[r] * conj_plus_iconj(ap[H - 1 - r], bp[r]);
+        });
+        if (lane0) {
+            sfor<0, H>([&](auto Rr) QT_INL {
+                constexpr int r = Rr;
+                if constexpr (r == 0) {
+                    v[0] = mk(2.0f * apM.re, -2.0f * apM.im);
+                } else {
+                    v[r] = ea[r] * conj_plus_iconj(ap[H - r], ap[r]);
+                }
+                v[H + r] = eb[r] * conj_plus_iconj(bp[H - 1 - r], bp[r]);
+            });
         }
         // two exchange buffers (together the size of the FP64 one): the
         // first FFT exchanges through X, Y, X, ..., the second starts with
@@ -228,7 +234,6 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
         // C^T: U = conj(v); a+'_j = i (e_j U_{M-j} - conj(e_j) U_j), e_j =
         // e^{-i pi j/N}; a+'_M = 2 U_0 (lane 0)
         {
-            const cx<float>* wd = opaque(tb.wd);
             auto tmix = [](cx<float> e, cx<float> um, cx<float> u) QT_INL {
                 // i (e conj(um') - conj(e) conj(u')) with um', u' the FFT outputs
                 const cx<float> p = e * conjf(um), q = conjf(e) * conjf(u);
@@ -237,8 +242,8 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
             };
             sfor<0, H>([&](auto Rr) QT_INL {
                 constexpr int r = Rr;
-                ap[r] = tmix(ldg(wd, ln.ja + r * T), v[H + H - 1 - r], v[r]);
-                bp[r] = tmix(ldg(wd, ln.jb + r * T), v[H - 1 - r], v[H + r]);
+                ap[r] = tmix(ea[r], v[H + H - 1 - r], v[r]);
+                bp[r] = tmix(eb[r], v[H - 1 - r], v[H + r]);
             });
             if (lane0) {
                 sfor<0, H>([&](auto Rr) QT_INL {
@@ -246,9 +251,9 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
                     if constexpr (r == 0) {
                         ap[0] = mk(0.0f, 0.0f);
                     } else {
-                        ap[r] = tmix(ldg(wd, r * T), v[H - r], v[r]);
+                        ap[r] = tmix(ea[r], v[H - r], v[r]);
                     }
-                    bp[r] = tmix(ldg(wd, W + r * T), v[H + H - 1 - r], v[H + r]);
+                    bp[r] = tmix(eb[r], v[H + H - 1 - r], v[H + r]);
                 });
             }
         }
