@@ -4,7 +4,7 @@ Tolerances:
   FP64 (fused and plain): wave function ||u_gpu - u_ora|| / ||u_ora|| <= 1e-10,
       norm and overlaps/survival probabilities within 1e-10 absolute (the
       two sides differ only in summation order and transform algorithm:
-      ~1e-15 per step, measured ~7e-13 after 1000 steps).
+      ~1e-15 per step, measured ~1e-12 after 1000 steps).
   FP32-bulk: single-precision rounding, 6e-8 per operation.  A step
       repeats nearly the same rounding error (the state changes little from
       one step to the next), so the error grows with the steps: measured
