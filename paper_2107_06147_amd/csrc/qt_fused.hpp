@@ -163,6 +163,9 @@ __device__ __forceinline__ void sincos_small(double x, double* s, double* c) { s
 // series suffice.
 template <class R, bool GAMMA, bool FAST>
 struct HalfStep {
+    // without the thermal phase C_m is the static phase: the same every step
+    // until a jump changes (l, colour), so a cache of it stays valid
+    static constexpr bool kStaticC = !GAMMA;
     const cx<R>* row;
     R dr, zr, zi;
     __device__ __forceinline__ R r2(int m) const
@@ -195,6 +198,7 @@ struct HalfStep {
         dm1 = em1(x2);
         C = phase(pre, x2);
     }
+    __device__ __forceinline__ R damping(int m) const { return em1(r2(m)); }
 };
 
 // The half-step factor of the isotropic KSU potential (appendix "Isotropic
@@ -211,6 +215,7 @@ constexpr double kKsuA = 0.409, kKsuSigma = 0.21;
 constexpr int kPhiFine = 4096, kPhiCoarse = 16256;   // intervals
 template <class R>
 struct HalfStepKSU {
+    static constexpr bool kStaticC = false;
     const cx<R>* phi_tab;     // (phi, phi'): kPhiFine + 1 fine, then kPhiCoarse + 1
     R dr, half_dt, md, cI, cent, vsb;
     __device__ __forceinline__ cx<R> preload(int) const { return mk(R(0), R(0)); }
@@ -269,29 +274,56 @@ __device__ __forceinline__ void ksu_medium(double T, double md_factor, double* m
     *cI = as * (4.0 / 3.0) * T;
 }
 
+// The static phase row of (l, colour) into this lane's slots of the cache
+// `fac` (slot E < R1: point ja + E T; slot R1 + E: point jb + E T).
+template <class R, int N, int W>
+__device__ __forceinline__ void fill_static_phase(cx<R>* fac, const cx<R>* row,
+                                                  const Lanes<N, W>& ln)
+{
+    constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
+    cx<R>* mine = fac + ln.t;
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        mine[Rr * W] = ldg(row, ln.ja + Rr * T);
+        mine[(R1 + Rr) * W] = ldg(row, ln.jb + Rr * T);
+    });
+}
+
 // First half-step: u <- C D u.  Returns this lane's part of sum |D u|^2 (the
-// norm the unitary block receives) when SUM; stores C_m in `fac` (this
-// lane's slots, no other lane reads them) when CACHE, and D_m - 1 in dm
-// (registers, for the second half-step).
-template <class R, int N, int W, class H, bool CACHE, bool SUM>
+// norm the unitary block receives) when SUM; D_m - 1 goes to dm (registers,
+// for the second half-step).  With CACHE, C_m is in `fac` (this lane's
+// slots, no other lane reads them) for the second half-step: stored here,
+// or, for a static C (H::kStaticC) when STATIC, already there
+// (fill_static_phase) and read from it instead of the table.
+template <class R, int N, int W, class H, bool CACHE, bool SUM, bool STATIC = false>
 __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
                                              const Lanes<N, W>& ln, cx<R>* fac, R* dm)
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
+    constexpr bool kCached = CACHE && STATIC && H::kStaticC;
     double acc = 0.0;
     cx<R>* mine = fac + ln.t;
-    // table data first: every load in flight at once
+    // table (or cache) data first: every load in flight at once
     cx<R> pr[2 * R1];
     sfor<0, R1>([&](auto Rr) QT_INL {
-        pr[Rr] = h.preload(ln.ja + Rr * T);
-        pr[R1 + Rr] = h.preload(ln.jb + Rr * T);
+        if constexpr (kCached) {
+            pr[Rr] = mine[Rr * W];
+            pr[R1 + Rr] = mine[(R1 + Rr) * W];
+        } else {
+            pr[Rr] = h.preload(ln.ja + Rr * T);
+            pr[R1 + Rr] = h.preload(ln.jb + Rr * T);
+        }
     });
     auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
         cx<R> C;
-        h.factors(m, pr[E], dm[E], C);
+        if constexpr (kCached) {
+            dm[E] = h.damping(m);
+            C = pr[E];
+        } else {
+            h.factors(m, pr[E], dm[E], C);
+            if constexpr (CACHE) mine[E * W] = C;
+        }
         const cx<R> w = u + scale(u, dm[E]);
         if constexpr (SUM) acc += abs2d(w);
-        if constexpr (CACHE) mine[E * W] = C;
         u = C * w;
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
@@ -498,6 +530,7 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
     // per-lane cache of the phase factors C_m between the two half-steps of a
     // step, kept when it still leaves room for two workgroups per CU
     constexpr bool kCache = kBufBytes + sizeof(cx<R>) * N <= 80u * 1024u;
+    constexpr bool kStaticCache = kCache && W > 64;
     __shared__ cx<R> fac[kCache ? N : 1];
 
     const Lanes<N, W> ln(threadIdx.x);
@@ -590,6 +623,12 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
         const double xmax = (double)(N - 1) * g.dr * (double)(N - 1) * g.dr;
         int cur = 0;
         scl = uniform(scl);
+        // without the thermal phase the cache of C_m holds the static phase
+        // row of (l, colour) from here and after every jump (workgroups of
+        // several waves: with one wave, N = 1024, it measured 9% slower than
+        // reading the row every step)
+        const bool static_c = kStaticCache && !ksu && !has_gamma;
+        if (static_c && status == QT_TRAJ_OK) fill_static_phase<R, N, W>(fac, phase_row<R, N>(g, l, c), ln);
         while (status == QT_TRAJ_OK && step < end) {
             // lane-derived values are recomputed every step (see opaque_lane)
             const Lanes<N, W> ls(opaque_lane(threadIdx.x));
@@ -619,7 +658,8 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
             } else {
                 with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
                     const HalfStep<R, G, F> h{row, dr, zr, zi};
-                    n_in = first_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm>(a, b, h, ls, fac, dm);
+                    n_in = first_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm, kStaticCache>(
+                        a, b, h, ls, fac, dm);
                 });
             }
             if constexpr (kRenorm) {
@@ -692,6 +732,7 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
                     status = QT_TRAJ_LMAX;
                     break;
                 }
+                if (static_c) fill_static_phase<R, N, W>(fac, phase_row<R, N>(g, l, c), ls);
             }
         }
         const bool done = status != QT_TRAJ_OK || step >= g.n_steps;
