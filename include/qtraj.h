@@ -249,6 +249,15 @@ qt_status qt_cancel(qt_server* s, uint64_t id);
 qt_status qt_server_stats(qt_server* s, qt_stats* out);
 qt_status qt_server_destroy(qt_server* s);
 
+/* Number of time steps a run takes with this temperature table (paper: Sec.
+ * "Summary of QTraj execution": the evolution runs from tau_start in steps
+ * of dt while t_n = tau_start + n dt lies within the table and T(t_n), linear
+ * between the table's points, is at least T_final; at most max_steps).
+ * Uses phys->dt only.  Host computation, no device work, no context.
+ * QT_EINVAL for a null argument, dt not finite and > 0, or an invalid table
+ * (as qt_run). */
+qt_status qt_count_steps(const qt_physics* phys, const qt_ttable* ttable, int64_t* n_steps);
+
 /* Kernel timing of the most recent qt_run / qt_job_advance on this context:
  * milliseconds between HIP events recorded around its kernel launches on
  * the caller's stream (synchronises that stream). */

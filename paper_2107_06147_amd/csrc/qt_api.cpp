@@ -56,21 +56,54 @@ double host_temperature(const double* tau, const double* T, int n, double t)
 
 int64_t count_steps(const qt_physics& p, const qt_ttable& tt)
 {
-    // the step count stops where the table ends or T drops below T_final
+    // The step count stops where the table ends or T(t_n) drops below
+    // T_final, with t_n = tau_start + n dt and T linear between the table's
+    // points (the interpolation the kernels use).  Steps are
+    // taken one by one only where that decision can go either way: a run of
+    // steps before the table or inside one of its intervals is passed at
+    // once when T there cannot fall below T_final (both ends of the
+    // interval above it by more than the interpolation's rounding).  t_n
+    // grows with n, so the first step past a point is found by an estimate
+    // and a correction.
+    const double* tau = tt.tau;
+    const double* Tt = tt.T;
+    const int last = tt.n - 1;
+    auto t_of = [&](int64_t n) { return tt.tau_start + (double)n * p.dt; };
+    // first n' > n with t_{n'} >= x (ge) or t_{n'} > x (!ge)
+    auto first_past = [&](int64_t n, double x, bool ge) {
+        auto past = [&](int64_t k) { return ge ? t_of(k) >= x : t_of(k) > x; };
+        const double est = std::ceil((x - tt.tau_start) / p.dt);
+        // (the estimate is off by a step at most: beyond the cap is beyond it)
+        if (est >= (double)tt.max_steps + 2.0) return tt.max_steps;
+        int64_t k = est > (double)n + 1.0 ? (int64_t)est : n + 1;
+        while (k > n + 1 && past(k - 1)) --k;
+        while (!past(k)) ++k;
+        return k;
+    };
+    const double eps = 4.0 * 2.220446049250313e-16;
     int64_t n = 0;
     int i = 0;
     while (n < tt.max_steps) {
-        const double t = tt.tau_start + (double)n * p.dt;
-        if (t > tt.tau[tt.n - 1]) break;
+        const double t = t_of(n);
+        if (t > tau[last]) break;
         double T;
-        if (t <= tt.tau[0]) {
-            T = tt.T[0];
-        } else if (t >= tt.tau[tt.n - 1]) {
-            T = tt.T[tt.n - 1];
+        if (t <= tau[0]) {
+            if (Tt[0] >= tt.T_final) {
+                n = std::min(first_past(n, tau[0], false), tt.max_steps);
+                continue;
+            }
+            T = Tt[0];
+        } else if (t >= tau[last]) {
+            T = Tt[last];
         } else {
-            while (!(tt.tau[i + 1] > t)) ++i;
-            const double w = (t - tt.tau[i]) / (tt.tau[i + 1] - tt.tau[i]);
-            T = tt.T[i] + (tt.T[i + 1] - tt.T[i]) * w;
+            while (!(tau[i + 1] > t)) ++i;
+            const double lo = std::min(Tt[i], Tt[i + 1]);
+            if (lo - eps * (std::fabs(Tt[i]) + std::fabs(Tt[i + 1])) >= tt.T_final) {
+                n = std::min(first_past(n, tau[i + 1], true), tt.max_steps);
+                continue;
+            }
+            const double w = (t - tau[i]) / (tau[i + 1] - tau[i]);
+            T = Tt[i] + (Tt[i + 1] - Tt[i]) * w;
         }
         if (T < tt.T_final) break;
         ++n;
@@ -82,6 +115,18 @@ static bool coulomb_state_known(int n, int l)
 {
     return (n == 1 && l == 0) || (n == 2 && (l == 0 || l == 1)) ||
            (n == 3 && (l >= 0 && l <= 2));
+}
+
+static qt_status validate_ttable(const qt_ttable* tt)
+{
+    if (!tt->tau || !tt->T || tt->n < 2) return fail(QT_EINVAL, "temperature table needs >= 2 points");
+    for (int i = 0; i + 1 < tt->n; ++i)
+        if (!(tt->tau[i + 1] > tt->tau[i])) return fail(QT_EINVAL, "tau must increase strictly");
+    for (int i = 0; i < tt->n; ++i)
+        if (!(tt->T[i] >= 0) || !std::isfinite(tt->T[i])) return fail(QT_EINVAL, "T must be finite and >= 0");
+    if (tt->max_steps < 0) return fail(QT_EINVAL, "max_steps must be >= 0");
+    if (!std::isfinite(tt->tau_start)) return fail(QT_EINVAL, "tau_start must be finite");
+    return QT_OK;
 }
 
 qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in, const qt_batch* b)
@@ -98,13 +143,7 @@ qt_status validate(const qt_physics* p, const qt_ttable* tt, const qt_init* in, 
     if (p->deriv_type != 0 && p->deriv_type != 1) return fail(QT_EINVAL, "deriv_type must be 0 or 1");
     if (!(p->r_max > 0) || p->r_max > 1) return fail(QT_EINVAL, "r_max must be in (0, 1]");
     if (p->flags & ~QT_FLAG_KINETIC_OFF) return fail(QT_EINVAL, "unknown flags 0x%x", p->flags);
-    if (!tt->tau || !tt->T || tt->n < 2) return fail(QT_EINVAL, "temperature table needs >= 2 points");
-    for (int i = 0; i + 1 < tt->n; ++i)
-        if (!(tt->tau[i + 1] > tt->tau[i])) return fail(QT_EINVAL, "tau must increase strictly");
-    for (int i = 0; i < tt->n; ++i)
-        if (!(tt->T[i] >= 0) || !std::isfinite(tt->T[i])) return fail(QT_EINVAL, "T must be finite and >= 0");
-    if (tt->max_steps < 0) return fail(QT_EINVAL, "max_steps must be >= 0");
-    if (!std::isfinite(tt->tau_start)) return fail(QT_EINVAL, "tau_start must be finite");
+    if (qt_status st = validate_ttable(tt); st != QT_OK) return st;
     if (in->l < 0 || in->l > 1000) return fail(QT_EINVAL, "initial l out of range");
     if (in->color != QT_SINGLET && in->color != QT_OCTET) return fail(QT_EINVAL, "color must be 0 or 1");
     switch (in->kind) {
@@ -822,6 +861,15 @@ qt_status qt_context_destroy(qt_context* ctx)
     hipEventDestroy(ctx->ev0);
     hipEventDestroy(ctx->ev1);
     delete ctx;
+    return QT_OK;
+}
+
+qt_status qt_count_steps(const qt_physics* phys, const qt_ttable* ttable, int64_t* n_steps)
+{
+    if (!phys || !ttable || !n_steps) return fail(QT_EINVAL, "null argument");
+    if (!(phys->dt > 0) || !std::isfinite(phys->dt)) return fail(QT_EINVAL, "dt must be finite and > 0");
+    if (qt_status st = validate_ttable(ttable); st != QT_OK) return st;
+    *n_steps = count_steps(*phys, *ttable);
     return QT_OK;
 }
 

@@ -107,6 +107,7 @@ _SIGS = {
     "qt_last_kernel_ms": (C.c_int, [_VP, _D, _I64]),
     "qt_plan": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _I32, _I32]),
     "qt_eigen_basis": (C.c_int, [_VP, C.POINTER(qt_physics), _D, _D]),
+    "qt_count_steps": (C.c_int, [C.POINTER(qt_physics), C.POINTER(qt_ttable), _I64]),
     "qt_last_error": (C.c_char_p, []),
     "qt_version": (C.c_char_p, []),
 }
@@ -299,6 +300,17 @@ def eigen_basis(ctx, cfg):
     check(lib().qt_eigen_basis(ctx.h, C.byref(p), e.ctypes.data_as(_D), b.ctypes.data_as(_D)),
           "qt_eigen_basis")
     return e, b
+
+
+def count_steps(cfg):
+    """qt_count_steps: the number of time steps a run of this config takes
+    (host computation, no device)."""
+    keep = []
+    p = physics(cfg)
+    tt = ttable(cfg, keep)
+    n = C.c_int64(0)
+    check(lib().qt_count_steps(C.byref(p), C.byref(tt), C.byref(n)), "qt_count_steps")
+    return n.value
 
 
 def _stream_handle(stream):

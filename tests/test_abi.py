@@ -59,3 +59,53 @@ def test_oracle_and_library_share_no_code():
     for f in ("qtraj.py", "__init__.py", "build.py"):
         txt = open(os.path.join(ROOT, "paper_2107_06147_amd", f)).read()
         assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+def test_count_steps_matches_the_stepwise_definition(qtlib):
+    """qt_count_steps (host only) passes whole intervals of the table at once
+    where T cannot cross T_final; the oracle takes every step.  The two agree
+    on Bjorken and random-walk (non-monotone) tables, starts before, inside
+    and at the table's points, steps that land exactly on points, T_final
+    equal to a point's T, and step caps."""
+    import numpy as np
+    import oracle
+    from paper_2107_06147_amd import workloads as W
+    rng = np.random.default_rng(7)
+    cases = 0
+    for trial in range(300):
+        kind = trial % 4
+        dt = float(rng.choice([0.001, 0.0005, 0.0123, 0.25, 0.5]))
+        if kind == 0:
+            tau, T = W.bjorken_table(float(rng.uniform(0.3, 0.55)), float(rng.uniform(0.4, 0.8)), 0.25,
+                                     int(rng.integers(2, 60)))
+            tf = float(rng.choice([0.25, 0.3, 0.0, float(T[len(T) // 2])]))
+        elif kind == 1:
+            tau, T = W.random_walk_table(rng, n_points=int(rng.integers(5, 80)))
+            tf = float(rng.choice([0.3, 0.4, float(T[int(rng.integers(len(T)))])]))
+        elif kind == 2:
+            # points on multiples of dt: steps land exactly on them
+            k = np.cumsum(rng.integers(1, 6, size=int(rng.integers(2, 12))))
+            tau = (k - k[0]).astype(float) * dt
+            T = rng.choice([0.2, 0.3, 0.4], size=len(tau)).astype(float)
+            tf = float(rng.choice([0.2, 0.3, 0.4]))
+        else:
+            tau = np.sort(rng.uniform(0.0, 50.0, size=int(rng.integers(2, 30))))
+            tau = np.unique(tau)
+            if len(tau) < 2:
+                continue
+            T = rng.uniform(0.0, 1.0, size=len(tau))
+            tf = float(rng.uniform(0.0, 0.5))
+        span = float(tau[-1] - tau[0])
+        start = float(rng.choice([tau[0], tau[0] - 3.5 * dt, tau[0] + 0.3 * span,
+                                  float(tau[len(tau) // 2]), tau[-1]]))
+        cap = int(rng.choice([0, 1, 7, 1000, 2 ** 62]))
+        cfg = W.base(N=256, dt=dt, tau=np.asarray(tau, float), T=np.asarray(T, float),
+                     tau_start=start, T_final=tf, max_steps=cap)
+        assert qtlib.count_steps(cfg) == oracle.num_steps(cfg), (trial, kind, dt, start, tf, cap)
+        cases += 1
+    assert cases > 250
+    # an invalid table is rejected, as qt_run rejects it
+    bad = W.base(N=256, dt=0.001, tau=np.array([0.0, 0.0]), T=np.array([0.3, 0.3]),
+                 tau_start=0.0, T_final=0.0, max_steps=10)
+    with pytest.raises(RuntimeError):
+        qtlib.count_steps(bad)
