@@ -220,6 +220,27 @@ def results_struct(out, row=0):
                       p("status", _I32), p("steps_done", _I64), p("min_gap", _D), p("psi", _D))
 
 
+_RESULT_FIELDS = [f for f, _ in qt_results._fields_]
+
+
+def results_array(out, rows, keep):
+    """qt_results of the tensors in `out` for every start row in `rows` at
+    once (ctypes array; its pointer table is a numpy array kept in `keep`)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    base = np.zeros(len(_RESULT_FIELDS), dtype=np.int64)
+    step = np.zeros(len(_RESULT_FIELDS), dtype=np.int64)
+    for j, name in enumerate(_RESULT_FIELDS):
+        t = out.get(name)
+        if t is not None:
+            base[j] = t.data_ptr()
+            step[j] = t.stride(0) * t.element_size()
+    tab = base[None, :] + rows[:, None] * step[None, :]
+    tab[:, base == 0] = 0
+    tab = np.ascontiguousarray(tab.astype(np.uint64))
+    keep.append(tab)
+    return (qt_results * len(rows)).from_buffer(tab)
+
+
 def host_results(n, N, want_psi):
     """Output arrays in host memory (numpy) and their qt_results."""
     out = {
@@ -347,26 +368,23 @@ def run_many(ctx, cfgs, precision=QT_FP32_BULK, want_psi=False, stream=None, fla
     TT = (qt_ttable * k)()
     IN = (qt_init * k)()
     B = (qt_batch * k)()
-    RS = (qt_results * k)()
     outs = []
     if flat:
         if want_psi:
             raise ValueError("flat results hold no wave functions")
-        total = sum(int(c["n_traj"]) for c in cfgs)
-        flat_out, _ = alloc_results(total, 0, False)
-    row = 0
+        counts = np.array([int(c["n_traj"]) for c in cfgs], dtype=np.int64)
+        flat_out, _ = alloc_results(int(counts.sum()), 0, False)
+        RS = results_array(flat_out, np.concatenate([[0], np.cumsum(counts)[:-1]]), keep)
+    else:
+        RS = (qt_results * k)()
     for i, cfg in enumerate(cfgs):
-        if flat:
-            r = results_struct(flat_out, row)
-            row += int(cfg["n_traj"])
-        else:
-            o, r = alloc_results(int(cfg["n_traj"]), int(cfg["N"]), want_psi)
+        if not flat:
+            o, RS[i] = alloc_results(int(cfg["n_traj"]), int(cfg["N"]), want_psi)
             outs.append(o)
         P[i] = physics(cfg)
         TT[i] = ttable(cfg, keep)
         IN[i] = init(cfg, keep)
         B[i] = batch(cfg, precision, QT_FORM_FUSED)
-        RS[i] = r
     check(lib().qt_run_many(ctx.h, k, P, TT, IN, B, RS, _stream_handle(stream)), "qt_run_many")
     return flat_out if flat else outs
 
