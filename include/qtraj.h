@@ -269,6 +269,24 @@ qt_status qt_last_kernel_ms(qt_context* ctx, double* ms, int64_t* launches);
 qt_status qt_plan(qt_context* ctx, int32_t N, int32_t precision, int32_t tune,
                   int32_t* threads_per_traj, int32_t* traj_per_cu);
 
+/* Kernel variants of the fused form (Munich potential) for (N, precision):
+ * threads per trajectory of each, ascending, the first min(cap, count)
+ * written to threads (caller-owned, may be null when cap is 0); *count gets
+ * how many there are (0 for an N or precision without fused kernels).  Host
+ * query: no device work, no context.  The KSU potential has one variant per
+ * N, chosen by the library.  QT_EINVAL for a null count or a negative cap. */
+qt_status qt_plan_variants(int32_t N, int32_t precision, int32_t* threads, int32_t cap,
+                           int32_t* count);
+
+/* Fixes the kernel variant that runs (N, precision) on this context: one of
+ * the threads-per-trajectory values of qt_plan_variants, instead of the
+ * default or the tuned one (a later qt_plan with tune=1 keeps it).  For
+ * reproducible launch configurations, and to test every variant.  Queries
+ * the device's residency of that kernel.  QT_EINVAL for a null context or
+ * a variant that does not exist; QT_EDEVICE if the kernel cannot be
+ * resident. */
+qt_status qt_plan_set(qt_context* ctx, int32_t N, int32_t precision, int32_t threads_per_traj);
+
 /* Vacuum eigenstates 1S, 2S, 1P, 3S, 2P, 1D of the discrete Hamiltonian
  * (paper: Sec. "Using the built-in eigensolvers"; the states that initType
  * 100 starts from and ProjType 1 projects on).  The Hamiltonian is the one

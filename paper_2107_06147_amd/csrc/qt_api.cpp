@@ -1254,6 +1254,36 @@ qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys
     return st;
 }
 
+qt_status qt_plan_variants(int32_t N, int32_t precision, int32_t* threads, int32_t cap,
+                           int32_t* count)
+{
+    if (!count || cap < 0 || (cap > 0 && !threads)) return fail(QT_EINVAL, "null argument or negative cap");
+    int Ws[16];
+    const int n = fused_variants(precision, N, Ws, 16);
+    std::sort(Ws, Ws + n);
+    for (int i = 0; i < n && i < cap; ++i) threads[i] = Ws[i];
+    *count = n;
+    return QT_OK;
+}
+
+qt_status qt_plan_set(qt_context* ctx, int32_t N, int32_t precision, int32_t threads_per_traj)
+{
+    if (!ctx) return fail(QT_EINVAL, "null context");
+    if (!fused_get(precision, N, threads_per_traj))
+        return fail(QT_EINVAL, "no fused kernel for N=%d precision=%d with %d threads per trajectory",
+                    N, precision, threads_per_traj);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    QT_HIP(hipSetDevice(ctx->device));
+    qt_context::Variant v;
+    v.W = threads_per_traj;
+    v.slots_per_cu = fused_occupancy(precision, N, threads_per_traj);
+    v.tuned = true;
+    if (v.slots_per_cu <= 0)
+        return fail(QT_EDEVICE, "kernel N=%d W=%d cannot be resident", N, threads_per_traj);
+    ctx->plans[std::make_pair(precision, N)] = v;
+    return QT_OK;
+}
+
 qt_status qt_plan(qt_context* ctx, int32_t N, int32_t precision, int32_t tune,
                   int32_t* threads_per_traj, int32_t* traj_per_cu)
 {

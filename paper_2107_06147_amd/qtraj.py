@@ -108,6 +108,8 @@ _SIGS = {
     "qt_plan": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, _I32, _I32]),
     "qt_eigen_basis": (C.c_int, [_VP, C.POINTER(qt_physics), _D, _D]),
     "qt_count_steps": (C.c_int, [C.POINTER(qt_physics), C.POINTER(qt_ttable), _I64]),
+    "qt_plan_variants": (C.c_int, [C.c_int32, C.c_int32, _I32, C.c_int32, _I32]),
+    "qt_plan_set": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32]),
     "qt_last_error": (C.c_char_p, []),
     "qt_version": (C.c_char_p, []),
 }
@@ -303,6 +305,11 @@ class Context:
         check(lib().qt_last_kernel_ms(self.h, C.byref(ms), C.byref(n)), "qt_last_kernel_ms")
         return ms.value, n.value
 
+    def plan_set(self, N, precision, threads_per_traj):
+        """Fix the fused kernel variant for (N, precision) (qt_plan_set)."""
+        check(lib().qt_plan_set(self.h, int(N), int(precision), int(threads_per_traj)),
+              "qt_plan_set")
+
     def plan(self, N, precision, tune=False):
         w = C.c_int32()
         s = C.c_int32()
@@ -321,6 +328,15 @@ def eigen_basis(ctx, cfg):
     check(lib().qt_eigen_basis(ctx.h, C.byref(p), e.ctypes.data_as(_D), b.ctypes.data_as(_D)),
           "qt_eigen_basis")
     return e, b
+
+
+def plan_variants(N, precision):
+    """Threads per trajectory of every fused kernel variant for (N, precision)
+    (qt_plan_variants; host query)."""
+    n = C.c_int32(0)
+    buf = (C.c_int32 * 16)()
+    check(lib().qt_plan_variants(int(N), int(precision), buf, 16, C.byref(n)), "qt_plan_variants")
+    return [int(buf[i]) for i in range(min(n.value, 16))]
 
 
 def count_steps(cfg):

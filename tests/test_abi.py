@@ -109,3 +109,16 @@ def test_count_steps_matches_the_stepwise_definition(qtlib):
                  tau_start=0.0, T_final=0.0, max_steps=10)
     with pytest.raises(RuntimeError):
         qtlib.count_steps(bad)
+
+
+def test_plan_variants_host_query(qtlib):
+    """The fused kernel variants are listed without a device; every N from
+    256 to 8192 has at least one in each precision."""
+    for N in (256, 512, 1024, 2048, 4096, 8192):
+        for prec in (qtlib.QT_FP64, qtlib.QT_FP32_BULK):
+            ws = qtlib.plan_variants(N, prec)
+            assert ws and ws == sorted(ws) and all(w % 64 == 0 and N % w == 0 for w in ws), (N, prec, ws)
+    assert 128 in qtlib.plan_variants(2048, qtlib.QT_FP32_BULK)
+    assert qtlib.plan_variants(3000, qtlib.QT_FP64) == []
+    L = qtlib.lib()
+    assert L.qt_plan_variants(2048, 0, None, 0, None) == qtlib.QT_EINVAL

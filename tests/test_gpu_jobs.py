@@ -22,9 +22,9 @@ def ctx():
     c.close()
 
 
-def _cfg():
-    return W.base(N=512, L=20.0, dt=0.001, kappa_hat=20.0, n_traj=40, seed=17,
-                  init_kind=W.INIT_GAUSSIAN, init_width=1.0, **W.constant_T(0.5, 300))
+def _cfg(N=512, steps=300):
+    return W.base(N=N, L=N * 20.0 / 512, dt=0.001, kappa_hat=20.0, n_traj=40, seed=17,
+                  init_kind=W.INIT_GAUSSIAN, init_width=1.0, **W.constant_T(0.5, steps))
 
 
 def _same(a, b, keys=KEYS + ("psi",)):
@@ -33,13 +33,18 @@ def _same(a, b, keys=KEYS + ("psi",)):
             assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
 
 
+@pytest.mark.parametrize("N,steps", [(512, 300), (2048, 120)])
 @pytest.mark.parametrize("prec", [F32, F64])
-def test_segments_equal_single_run(ctx, prec):
+def test_segments_equal_single_run(ctx, prec, N, steps):
+    """Also at N = 2048, where workgroups of several waves keep the static
+    phase cached across steps (filled again after each jump and at each
+    resumed segment)."""
     import torch
-    cfg = _cfg()
+    cfg = _cfg(N, steps)
     ref = gpu_run(ctx, cfg, prec)
+    assert ref["n_jumps"].sum() > 0
     job = qt.Job(ctx, cfg, precision=prec, segment_steps=37)
-    job.advance(300)
+    job.advance(steps)
     assert job.done()
     out = qt.to_numpy(job.results(want_psi=True))
     torch.cuda.synchronize()

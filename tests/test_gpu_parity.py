@@ -114,6 +114,49 @@ def test_grid_sizes(ctx, N, prec):
     print(N, prec, compare(ref, out, prec, label="N=%d" % N))
 
 
+# ------------------------------------------------- every kernel variant
+
+@pytest.mark.parametrize("N", [256, 512, 1024, 2048, 4096, 8192])
+def test_every_kernel_variant(N):
+    """Each fused kernel variant (threads per trajectory) of each precision,
+    fixed with qt_plan_set, and the KSU kernel of this N, against the oracle:
+    the tuner may pick any of them (the benchmark runs the tuned ones)."""
+    steps = {256: 120, 512: 100, 1024: 80, 2048: 50, 4096: 24, 8192: 10}[N]
+    cfg = W.base(N=N, L=N * 5.0 / 256.0, dt=0.001, kappa_hat=50.0, n_traj=2, seed=21,
+                 init_kind=W.INIT_GAUSSIAN, init_width=1.0, init_l=1, **W.constant_T(0.5, steps))
+    ref = oracle.run(cfg, want_psi=True)
+    tau, T = W.bjorken_table(0.5, 0.6, 0.2, 50)
+    ksu = W.base(N=N, L=N * 5.0 / 256.0, dt=0.002, potential=W.POTENTIAL_KSU, md_factor=1.2,
+                 do_jumps=0, kappa_hat=0.0, n_traj=2, seed=22, tau=tau, T=T,
+                 tau_start=float(tau[0]), T_final=0.2, max_steps=steps,
+                 init_kind=W.INIT_GAUSSIAN, init_l=0, init_width=2.0)
+    ref_ksu = oracle.run(ksu, want_psi=True)
+    for prec in (F64, F32):
+        variants = qt.plan_variants(N, prec)
+        assert variants
+        for w in variants:
+            c = qt.Context(0)
+            try:
+                c.plan_set(N, prec, w)
+                assert c.plan(N, prec)[0] == w
+                out = gpu_run(c, cfg, prec)
+                print("variant", N, prec, w, compare(ref, out, prec, label="N=%d W=%d" % (N, w)))
+            finally:
+                c.close()
+        c = qt.Context(0)
+        try:
+            out = gpu_run(c, ksu, prec)
+            print("ksu variant", N, prec, compare(ref_ksu, out, prec, label="ksu N=%d" % N))
+        finally:
+            c.close()
+    with pytest.raises(qt.QtError):
+        c = qt.Context(0)
+        try:
+            c.plan_set(N, F32, 7)
+        finally:
+            c.close()
+
+
 # ------------------------------------- C2 at full size, sampled trajectories
 
 C2_SAMPLE = [0, 1, 2047, 4095]
@@ -126,6 +169,8 @@ def test_c2_full_batch_sampled(ctx, prec, form):
     trajectory against the invariants."""
     cfg = W.c2_headline(kappa_hat=4.0, gamma_hat=-2.0)
     cfg["max_steps"] = 120
+    if form == FUSED:
+        ctx.plan(2048, prec, tune=True)     # the variant the benchmark runs
     out = gpu_run(ctx, cfg, prec, form, want_psi=False)
     assert np.all(out["steps_done"] == 120) or np.all(out["status"] != qt.QT_TRAJ_OK)
     assert np.all((out["norm"] > 0) & (out["norm"] <= 1.0 + 1e-6))
