@@ -204,3 +204,32 @@ def test_eigen_basis_and_ksu_through_jobs_and_server(ctx):
     srv.close()
     for c, o in zip((eig, ksu), outs):
         _same(gpu_run(ctx, c, F32), o)
+
+
+def test_c5_full_batch_sampled(ctx):
+    """The N = 4096 batch of 65,536 trajectories (three initial states) in
+    the benchmark's configuration (tuned variant, segmented jobs replayed as
+    HIP graphs), truncated to 40 steps: every trajectory against the
+    invariants, the first and last of each initial state against the
+    oracle."""
+    import torch
+    cfgs = W.c5_roofline(n_steps=40)
+    assert sum(int(c["n_traj"]) for c in cfgs) == 65536
+    ctx.plan(4096, F32, tune=True)
+    jobs = [qt.Job(ctx, c, precision=F32, segment_steps=20) for c in cfgs]
+    for j in jobs:
+        j.advance(40)
+    outs = [qt.to_numpy(j.results()) for j in jobs]
+    torch.cuda.synchronize()
+    for j in jobs:
+        j.close()
+    for cfg, out in zip(cfgs, outs):
+        assert np.all(out["steps_done"] == 40)
+        assert np.all((out["norm"] > 0) & (out["norm"] <= 1.0 + 1e-6))
+        assert np.all((out["l"] - cfg["init_l"] - out["n_jumps"]) % 2 == 0)
+        for k in (0, int(cfg["n_traj"]) - 1):
+            tid = int(cfg["traj_id0"]) + 3 * k
+            ref = oracle.run(cfg, n_traj=1, traj_id0=tid)
+            one = {key: v[k:k + 1] for key, v in out.items()}
+            compare(ref, one, F32, check_psi=False, label="c5 id %d" % tid)
+
