@@ -11,9 +11,11 @@ qt_run, which is part of the timed region).
 value      FP32-bulk fused form (FP32 wave function and transforms, FP64 norm
            and threshold), whole-job trajectory-steps/s.
 extra      FP64 plain (unfused) and FP64 fused throughput on the same
-           workload, the FP32-bulk speedup over the plain FP64 form, and
-           p50/p99 request latency of a shortened served stream when the
-           server is available.
+           workload, the FP32-bulk speedup over the plain FP64 form, FP32
+           against FP64 on one full run (near-threshold counts, jump
+           histories, largest differences away from the thresholds), the
+           uneven mixed-N batch, and p50/p99 request latency of a shortened
+           served stream.
 roofline   the fused kernel, algorithmic flops per trajectory-step
            F(N) = 10 N log2 N + 29 N (two complex DSTs at 5 N log2 N, three
            complex multiplies, norm and kernel arithmetic), divided by its
@@ -159,6 +161,35 @@ def uneven_leg(ctx, qt, W, torch):
             "lifetime_steps_min_max": [int(steps.min()), int(steps.max())]}
 
 
+def precision_leg(ctx, qt, run, out64, n_traj, N, torch):
+    """FP32-bulk against FP64 (the results in out64) on the same full run,
+    outside the timed region: how many trajectories pass near a jump
+    threshold (their smallest |norm - r| within the FP32 error, where the
+    two precisions may jump one step apart), whether the jump histories
+    agree, and the largest differences of the others."""
+    import numpy as np
+    b = qt.to_numpy(out64)
+    out, _ = qt.alloc_results(n_traj, N, False)
+    qt.run(ctx, run, precision=qt.QT_FP32_BULK, out=out)
+    torch.cuda.synchronize()
+    a = qt.to_numpy(out)
+    gap = np.minimum(a["min_gap"], b["min_gap"])
+    same = np.ones(n_traj, bool)
+    for k in ("n_jumps", "l", "color", "status", "steps_done"):
+        same &= a[k] == b[k]
+    far = same & (gap > 1e-4)
+    rel = np.abs(a["norm"] - b["norm"]) / np.maximum(b["norm"], 1e-300)
+    return {"run": "kappa_hat=4, gamma_hat=0 (the FP64 legs' run)",
+            "trajectories": int(n_traj),
+            "near_threshold_5e-5": int((gap <= 5e-5).sum()),
+            "near_threshold_1e-4": int((gap <= 1e-4).sum()),
+            "jump_histories_equal": int(same.sum()),
+            "far_from_thresholds": int(far.sum()),
+            "far_norm_rel_max": float(rel[far].max()) if far.any() else None,
+            "far_overlap_max": float(np.abs(a["overlap"][far] - b["overlap"][far]).max()) if far.any() else None,
+            "far_survival_max": float(np.abs(a["survival"][far] - b["survival"][far]).max()) if far.any() else None}
+
+
 def segments_leg(ctx, qt, W, torch):
     """N=4096, 65,536 trajectories (three initial states), 20,000 steps as
     two captured segments of 10,000 steps, checkpointed every 1,000."""
@@ -246,6 +277,7 @@ def main():
     extra["speedup_fp32_bulk_over_fp64_fused"] = value / extra["fp64_fused_traj_steps_per_s"]
     extra["plan"] = {"fp32_threads_per_traj": w32, "fp32_traj_per_cu": s32,
                      "fp64_threads_per_traj": w64, "fp64_traj_per_cu": s64}
+    extra["fp32_vs_fp64"] = precision_leg(ctx, qt, runs[2], out32, n_traj, N, torch)
 
     extra["c2_no_jump_shortcut"] = shortcut_leg(ctx, qt, runs, out32, torch)
     if not args.no_c3:
