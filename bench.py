@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--c5", action="store_true",
                     help="also run the N=4096 checkpointed-segments workload (about a minute)")
     ap.add_argument("--cpu-steps", type=int, default=300)
-    ap.add_argument("--profile", choices=["fp32", "fp64", "plain"], default=None,
+    ap.add_argument("--profile", choices=["fp32", "fp64", "plain", "c5"], default=None,
                     help="profiling mode: one short run of the batch (--profile-steps time "
                          "steps) in the given form, then a 256 MiB device copy that "
                          "calibrates HBM byte counters; prints no JSON")
@@ -92,18 +92,32 @@ def profile_mode(args):
     from paper_2107_06147_amd import workloads as W
     torch.cuda.set_device(0)
     ctx = qt.Context(0)
-    prec = qt.QT_FP64 if args.profile in ("fp64", "plain") else qt.QT_FP32_BULK
-    form = qt.QT_FORM_PLAIN if args.profile == "plain" else qt.QT_FORM_FUSED
-    if form == qt.QT_FORM_FUSED:
-        ctx.plan(2048, prec, tune=True)
-    cfg = W.c2_headline(4.0, 0.0)
-    cfg["max_steps"] = args.profile_steps
-    out, _ = qt.alloc_results(cfg["n_traj"], 2048, False)
-    qt.run(ctx, cfg, precision=prec, form=form, out=out)
-    torch.cuda.synchronize()
-    ms, launches = ctx.last_kernel_ms()
-    tps = int(out["steps_done"].sum().item())
-    print("profile %s: %d trajectory-steps, %.3f ms over %d launches" % (args.profile, tps, ms, launches))
+    if args.profile == "c5":
+        # the N=4096 batch of 65,536 trajectories through segmented jobs
+        ctx.plan(4096, qt.QT_FP32_BULK, tune=True)
+        cfgs = W.c5_roofline(n_steps=args.profile_steps)
+        seg = max(1, args.profile_steps // 2)
+        jobs = [qt.Job(ctx, c, precision=qt.QT_FP32_BULK, segment_steps=seg) for c in cfgs]
+        for j in jobs:
+            j.advance(args.profile_steps)
+        torch.cuda.synchronize()
+        tps = sum(int(j.results()["steps_done"].sum().item()) for j in jobs)
+        for j in jobs:
+            j.close()
+        print("profile c5: %d trajectory-steps in segments of %d steps" % (tps, seg))
+    else:
+        prec = qt.QT_FP64 if args.profile in ("fp64", "plain") else qt.QT_FP32_BULK
+        form = qt.QT_FORM_PLAIN if args.profile == "plain" else qt.QT_FORM_FUSED
+        if form == qt.QT_FORM_FUSED:
+            ctx.plan(2048, prec, tune=True)
+        cfg = W.c2_headline(4.0, 0.0)
+        cfg["max_steps"] = args.profile_steps
+        out, _ = qt.alloc_results(cfg["n_traj"], 2048, False)
+        qt.run(ctx, cfg, precision=prec, form=form, out=out)
+        torch.cuda.synchronize()
+        ms, launches = ctx.last_kernel_ms()
+        tps = int(out["steps_done"].sum().item())
+        print("profile %s: %d trajectory-steps, %.3f ms over %d launches" % (args.profile, tps, ms, launches))
     src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
