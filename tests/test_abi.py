@@ -122,3 +122,27 @@ def test_plan_variants_host_query(qtlib):
     assert qtlib.plan_variants(3000, qtlib.QT_FP64) == []
     L = qtlib.lib()
     assert L.qt_plan_variants(2048, 0, None, 0, None) == qtlib.QT_EINVAL
+
+
+def test_results_pointer_table_matches_per_batch_structs(qtlib):
+    """run_many's flat results: the pointer table built at once equals the
+    qt_results built batch by batch (host tensors; nothing is launched)."""
+    import torch
+    counts = [3, 1, 7, 2]
+    total = sum(counts)
+    out = {n: torch.zeros(total, dtype=torch.float64) for n in ("norm", "first_r", "mean_r", "min_gap")}
+    out["overlap"] = torch.zeros(total, 6, dtype=torch.float64)
+    out["survival"] = torch.zeros(total, 6, dtype=torch.float64)
+    for n in ("l", "color", "n_jumps", "status"):
+        out[n] = torch.zeros(total, dtype=torch.int32)
+    out["steps_done"] = torch.zeros(total, dtype=torch.int64)
+    rows = [0, 3, 4, 11]
+    keep = []
+    arr = qtlib.results_array(out, rows, keep)
+    for i, row in enumerate(rows):
+        one = qtlib.results_struct(out, row)
+        for f in qtlib._RESULT_FIELDS:
+            a = ctypes.cast(getattr(arr[i], f), ctypes.c_void_p).value
+            b = ctypes.cast(getattr(one, f), ctypes.c_void_p).value
+            assert a == b, (i, f)
+    assert ctypes.cast(arr[2].psi, ctypes.c_void_p).value is None      # no wave functions: null
