@@ -168,13 +168,23 @@ typedef struct {
  * may be NULL.  overlap/survival hold 6 values per trajectory; psi holds N
  * complex doubles (re, im interleaved) per trajectory; min_gap is the
  * smallest |norm - threshold| over all jump decisions (diagnostic for
- * comparisons near the threshold). */
+ * comparisons near the threshold).
+ * jump_log (qt_run and qt_run_many only; NULL for jobs and the server) holds
+ * jump_log_cap entries of 3 int32 per trajectory, entry e of trajectory i at
+ * jump_log[3 (i jump_log_cap + e)]: the step n (0-based) after which the
+ * e-th jump happened, and l and colour after it (paper: Sec. "The waiting
+ * time approach": the jump times of the waiting-time method; Sec. "Summary
+ * of QTraj execution", step 4).  The first min(n_jumps, jump_log_cap)
+ * entries are written, the rest are left as they were.  jump_log_cap >= 0. */
 typedef struct {
     double  *norm, *first_r, *overlap, *survival, *mean_r;
     int32_t *l, *color, *n_jumps, *status;
     int64_t *steps_done;
     double  *min_gap;
     double  *psi;
+    int32_t *jump_log;
+    int32_t  jump_log_cap;
+    int32_t  pad0;
 } qt_results;
 
 typedef struct qt_context qt_context;
@@ -206,8 +216,10 @@ qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys
 /* Segmented runs with checkpoints (FUSED form).  A job holds every
  * trajectory's state (wave function, step, l, colour, threshold, counters)
  * in device memory between segments.  qt_job_advance runs every unfinished
- * trajectory for up to `steps` more steps (a replay of a captured HIP
- * graph of launches of `segment_steps` steps each), then the state is a
+ * trajectory for `steps` more steps, or to its end if that comes first (a
+ * replay of a captured HIP graph of launches of `segment_steps` steps each,
+ * the last one of the remainder when `steps` is not a multiple), then the
+ * state is a
  * checkpoint: qt_job_save copies it to `dst` (host or device, state_bytes),
  * qt_job_load restores it into a job created with identical arguments. */
 qt_status qt_job_create(qt_context* ctx, const qt_physics* phys, const qt_ttable* tt,
@@ -225,7 +237,11 @@ qt_status qt_job_destroy(qt_job* job);
  * others run, as device memory within hbm_budget_bytes and persistent slots
  * free up; admission happens at segment boundaries of segment_steps steps.
  * qt_submit copies its inputs and returns at once; qt_wait copies a finished
- * request's results to HOST pointers. */
+ * request's results to HOST pointers.  A request that could not run (its
+ * device memory could not be allocated at admission, a launch or the copy
+ * of its results failed) ends with that cause: qt_wait returns QT_ENOMEM or
+ * QT_EDEVICE for it, QT_ECANCELED only after qt_cancel.  The kernel variant
+ * of each grid size is fixed at its first use for the server's life. */
 typedef struct {
     size_t  hbm_budget_bytes;     /* 0: 50% of free device memory             */
     int64_t segment_steps;        /* steps per admission round (e.g. 500)     */

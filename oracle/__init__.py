@@ -217,6 +217,8 @@ def run(cfg, n_traj=None, traj_id0=None, want_psi=False, want_trace=False,
     if want_psi:
         out["psi"] = out["psi"][..., 0] + 1j * out["psi"][..., 1]
     out["n_steps"] = n_steps
+    out["init_l"] = int(cfg.get("init_l", 0))
+    out["init_color"] = int(cfg.get("init_color", SINGLET))
     return out
 
 

@@ -399,24 +399,6 @@ qt_status prepare(qt_context* ctx, const qt_physics* p, const qt_ttable* tt, con
 
 // -------------------------------------------------- per-N device tables ---
 
-// Rounds a unit complex number to FP32 choosing, among the neighbours within
-// one ulp per component, the one whose modulus is closest to 1.
-static void round_unit_f32(double c, double s, float* out)
-{
-    const float c0 = (float)c, s0 = (float)s;
-    float bc = c0, bs = s0;
-    double be = std::fabs((double)c0 * c0 + (double)s0 * s0 - 1.0);
-    const float cs[3] = {std::nextafter(c0, -2.f), c0, std::nextafter(c0, 2.f)};
-    const float ss[3] = {std::nextafter(s0, -2.f), s0, std::nextafter(s0, 2.f)};
-    for (float ci : cs)
-        for (float si : ss) {
-            const double e = std::fabs((double)ci * ci + (double)si * si - 1.0);
-            if (e < be) { be = e; bc = ci; bs = si; }
-        }
-    out[0] = bc;
-    out[1] = bs;
-}
-
 qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* out)
 {
     auto key = std::make_pair(prec, N);
@@ -441,24 +423,26 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
     if (f32) {
         // the FP32 sine transform (split form, qt_dst32.hpp), one block:
         // FP32 [FFT twiddles of length M = N/2, rounding a | exp(-i pi j/N),
-        // j < M | FFT twiddles, rounding b], FP64 [FFT twiddles, DST-I
-        // weights of length M | the same of length N].  Rounding a is to
-        // nearest; b rounds 2w - a, so that (a + b)/2 lies closer to w than
-        // either.  The kernel alternates the two step by step: the rounding
-        // error of the twiddles, the same every step with one table, then
-        // largely cancels between consecutive steps instead of adding up.
+        // j < M, rounding a | the same two in rounding b], FP64 [FFT
+        // twiddles, DST-I weights of length M | the same of length N].
+        // Rounding a is to nearest; b rounds 2w - a, so that (a + b)/2 lies
+        // closer to w than either.  The kernel alternates the two step by
+        // step: the rounding error of these factors, the same every step
+        // with one table, then largely cancels between consecutive steps
+        // instead of adding up.
         // (The neighbour of modulus closest to 1 would trade the modulus
         // error for a larger phase error, which adds up the same way.)
         const int M = N / 2;
-        std::vector<float> f(6 * (size_t)M);
+        std::vector<float> f(8 * (size_t)M);
+        auto two = [&](size_t ia, size_t ib, double c, double s) {
+            f[2 * ia] = (float)c;
+            f[2 * ia + 1] = (float)s;
+            f[2 * ib] = (float)(2.0 * c - (double)f[2 * ia]);
+            f[2 * ib + 1] = (float)(2.0 * s - (double)f[2 * ia + 1]);
+        };
         for (int m = 0; m < M; ++m) {
-            const double c = std::cos(2.0 * kPi * m / M), s = -std::sin(2.0 * kPi * m / M);
-            f[2 * m] = (float)c;
-            f[2 * m + 1] = (float)s;
-            f[2 * (2 * (size_t)M + m)] = (float)(2.0 * c - (double)f[2 * m]);
-            f[2 * (2 * (size_t)M + m) + 1] = (float)(2.0 * s - (double)f[2 * m + 1]);
-            f[2 * ((size_t)M + m)] = (float)std::cos(kPi * m / N);
-            f[2 * ((size_t)M + m) + 1] = (float)-std::sin(kPi * m / N);
+            two(m, 2 * (size_t)M + m, std::cos(2.0 * kPi * m / M), -std::sin(2.0 * kPi * m / M));
+            two((size_t)M + m, 3 * (size_t)M + m, std::cos(kPi * m / N), -std::sin(kPi * m / N));
         }
         std::vector<double> d(4 * (size_t)M + 4 * (size_t)N);
         fill(M, &d[0], &d[2 * (size_t)M]);
@@ -582,7 +566,8 @@ constexpr int kLTab = 255;
 
 
 // exp(-i (dt/2) [V_coulomb(r_m) + l(l+1)/(M r_m^2)]) for l = 0..kLTab and
-// both colours (appendix "Munich potential"), rows [(2 l + c) N + m].
+// both colours (appendix "Munich potential"), rows [(2 l + c) N + m]; FP32
+// rows hold the factor minus one, (cos - 1, sin), each part rounded once.
 static void phase_table(const HostBatch& h, bool f32, char* dst)
 {
     const int N = h.phys.N;
@@ -593,15 +578,20 @@ static void phase_table(const HostBatch& h, bool f32, char* dst)
             const double coul = c == QT_SINGLET ? -alpha : alpha / 8.0;
             const double cent = (double)l * (l + 1) / h.phys.mass;
             for (int m = 0; m < N; ++m) {
-                double co = 1.0, sn = 0.0;
+                double co = 1.0, sn = 0.0, cm1 = 0.0;
                 if (m > 0) {
                     const double r = m * dr;
                     const double th = -0.5 * h.phys.dt * (coul / r + cent / (r * r));
                     co = std::cos(th);
                     sn = std::sin(th);
+                    const double sh = std::sin(0.5 * th);
+                    cm1 = -2.0 * sh * sh;            // cos th - 1, no cancellation
                 }
                 if (f32) {
-                    round_unit_f32(co, sn, reinterpret_cast<float*>(dst) + 2 * (row + m));
+                    // the factor minus one (the kernel applies u + (C - 1) u)
+                    float* d = reinterpret_cast<float*>(dst) + 2 * (row + m);
+                    d[0] = (float)cm1;
+                    d[1] = (float)sn;
                 } else {
                     double* d = reinterpret_cast<double*>(dst) + 2 * (row + m);
                     d[0] = co;
@@ -1201,6 +1191,7 @@ qt_status qt_run(qt_context* ctx, const qt_physics* phys, const qt_ttable* tt, c
                  const qt_batch* batch, const qt_results* dev_out, void* hip_stream)
 {
     if (!ctx || !dev_out) return fail(QT_EINVAL, "null argument");
+    if (dev_out->jump_log_cap < 0) return fail(QT_EINVAL, "jump_log_cap < 0");
     std::lock_guard<std::mutex> lk(ctx->mu);
     QT_HIP(hipSetDevice(ctx->device));
     HostBatch hb;
@@ -1230,6 +1221,7 @@ qt_status qt_run_many(qt_context* ctx, int32_t n_batches, const qt_physics* phys
     QT_HIP(hipSetDevice(ctx->device));
     std::vector<HostBatch> hbs(n_batches);
     for (int i = 0; i < n_batches; ++i) {
+        if (dev_out[i].jump_log_cap < 0) return fail(QT_EINVAL, "batch %d: jump_log_cap < 0", i);
         qt_status st = prepare(ctx, &phys[i], &tt[i], &init[i], &batch[i], &hbs[i]);
         if (st != QT_OK) return fail(st, "batch %d: %s", i, g_last_error.c_str());
         if (batch[i].form != QT_FORM_FUSED) return fail(QT_EINVAL, "batch %d: qt_run_many runs the fused form", i);

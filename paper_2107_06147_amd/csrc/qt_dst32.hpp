@@ -31,10 +31,10 @@
 // transpose of the first (kin_block32), so neither leaves its slots.
 //
 // Tables (one block, see ensure_tables): FP32 [FFT twiddles of length M |
-// e^{-i pi j/N}, j < M | the FFT twiddles in a second rounding], then FP64
+// e^{-i pi j/N}, j < M | the same two in a second rounding], then FP64
 // [FFT twiddles of length M | DST-I weights of length M | FFT twiddles of
 // length N | DST-I weights of length N].  The two roundings of the FP32
-// twiddles alternate step by step: their error, otherwise the same every
+// factors alternate step by step: their error, otherwise the same every
 // step, then largely cancels between consecutive steps.  The kinetic factors
 // are in the slot order of kin_block32 (below).
 #pragma once
@@ -51,13 +51,13 @@ struct Dst32Tables {
     const cx<double>* pre64h;  // DST-I weights, length M
     const cx<double>* tw64;    // FFT twiddles, length N
     const cx<double>* pre64;   // DST-I weights, length N
-    // the FP32 twiddles in rounding b when `second` (see ensure_tables)
+    // the FP32 factors in rounding b when `second` (see ensure_tables)
     __device__ __forceinline__ Dst32Tables(const void* base, bool second)
     {
         const char* p = static_cast<const char*>(base);
         tw32 = reinterpret_cast<const cx<float>*>(p) + (second ? 2 * M : 0);
-        wd = reinterpret_cast<const cx<float>*>(p) + M;
-        tw64h = reinterpret_cast<const cx<double>*>(p + 3 * (size_t)M * sizeof(cx<float>));
+        wd = reinterpret_cast<const cx<float>*>(p) + (second ? 3 * M : M);
+        tw64h = reinterpret_cast<const cx<double>*>(p + 4 * (size_t)M * sizeof(cx<float>));
         pre64h = tw64h + M;
         tw64 = pre64h + M;
         pre64 = tw64 + N;

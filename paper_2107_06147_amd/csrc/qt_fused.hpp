@@ -57,6 +57,35 @@ __device__ __forceinline__ void qsincos(float x, float* s, float* c)
 }
 __device__ __forceinline__ void qsincos(double x, double* s, double* c) { sincos(x, s, c); }
 
+// FP32 sin(x) and cos(x) - 1, the same reduction and series as qsincos, with
+// cos - 1 formed without adding 1 on the first quadrant: a phase factor of
+// small angle keeps its full relative accuracy in this form (cos x itself
+// rounds to 1 or 1 - 2^-24 there, a bias in the modulus of about x^2/2).
+__device__ __forceinline__ void qsincos_m1(float x, float* s, float* cm1)
+{
+    const float k = rintf(x * 0.636619772367581343f);
+    float f = fmaf(-k, 1.57079637050628662109375f, x);
+    f = fmaf(-k, -4.37113900018624283e-8f, f);
+    const float f2 = f * f;
+    float sp = -1.0f / 362880.0f;
+    sp = fmaf(sp, f2, 1.0f / 5040.0f);
+    sp = fmaf(sp, f2, -1.0f / 120.0f);
+    sp = fmaf(sp, f2, 1.0f / 6.0f);
+    sp = fmaf(-sp * f2, f, f);
+    float cp = -1.0f / 3628800.0f;
+    cp = fmaf(cp, f2, 1.0f / 40320.0f);
+    cp = fmaf(cp, f2, -1.0f / 720.0f);
+    cp = fmaf(cp, f2, 1.0f / 24.0f);
+    cp = fmaf(cp, f2, -0.5f);
+    const float cpm1 = cp * f2;                 // cos f - 1
+    const int q = (int)k & 3;
+    // q = 0: (sin, cos-1) = (sp, cpm1); 1: (cp, -sp - 1); 2: (-sp, -2 - cpm1);
+    // 3: (-cp, sp - 1), with cp = 1 + cpm1
+    const float c1 = 1.0f + cpm1;
+    *s = q == 0 ? sp : q == 1 ? c1 : q == 2 ? -sp : -c1;
+    *cm1 = q == 0 ? cpm1 : q == 1 ? -sp - 1.0f : q == 2 ? -2.0f - cpm1 : sp - 1.0f;
+}
+
 // kappa_hat at temperature T: the constant kappa_hat >= 0, or, for -1, -2,
 // -3, the central, lower and upper fits to lattice data of the appendix
 // "Munich potential", 1 / (a x^{3/2} + b x + c x^{1/2} + d) with
@@ -106,7 +135,8 @@ __device__ __forceinline__ void block_sum_vec(double* x, double* red)
 // of the half-step factor (appendix "Munich potential").  The host computes
 // it in FP64 for every (l, colour) with l <= l_tab, shared by all
 // trajectories of a grid; a half-step reads the row of its (l, colour) (L1/L2
-// resident: few rows are in use at a time).
+// resident: few rows are in use at a time).  FP32 rows hold the factor minus
+// one (see apply_phase).
 template <class R, int N>
 __device__ __forceinline__ const cx<R>* phase_row(const GroupDesc& g, int l, int c)
 {
@@ -148,17 +178,57 @@ __device__ __forceinline__ void sincos_small(float x, float* s, float* c)
 }
 __device__ __forceinline__ void sincos_small(double x, double* s, double* c) { sincos(x, s, c); }
 
+// FP32 sin(x) and cos(x) - 1 on |x| <= pi/4, cos - 1 without the 1 (see
+// qsincos_m1).
+__device__ __forceinline__ void sincos_small_m1(float x, float* s, float* cm1)
+{
+    const float x2 = x * x;
+    float sp = -1.0f / 362880.0f;
+    sp = fmaf(sp, x2, 1.0f / 5040.0f);
+    sp = fmaf(sp, x2, -1.0f / 120.0f);
+    sp = fmaf(sp, x2, 1.0f / 6.0f);
+    *s = fmaf(-sp * x2, x, x);
+    float cp = -1.0f / 3628800.0f;
+    cp = fmaf(cp, x2, 1.0f / 40320.0f);
+    cp = fmaf(cp, x2, -1.0f / 720.0f);
+    cp = fmaf(cp, x2, 1.0f / 24.0f);
+    cp = fmaf(cp, x2, -0.5f);
+    *cm1 = cp * x2;
+}
+
+// A unit phase factor C applied to w.  FP64 holds C and multiplies.  FP32
+// holds C - 1 (the host tables, the LDS cache and the per-step factors are
+// all in this form) and forms w + (C - 1) w, whose only full-size rounding
+// is the final addition: the modulus of C is then exact to the accuracy of
+// the small C - 1 instead of carrying the bias of a rounded cos near 1,
+// which is the same every step and grows the error linearly.
+__device__ __forceinline__ cx<double> apply_phase(cx<double> w, cx<double> C) { return C * w; }
+__device__ __forceinline__ cx<float> apply_phase(cx<float> w, cx<float> cm1)
+{
+    const float re = fmaf(cm1.re, w.re, -(cm1.im * w.im));
+    const float im = fmaf(cm1.re, w.im, cm1.im * w.re);
+    return mk(w.re + re, w.im + im);
+}
+// The product of two phase factors in the form apply_phase takes: C1 C2
+// (FP64), (C1 - 1) + (C2 - 1) + (C1 - 1)(C2 - 1) (FP32).
+__device__ __forceinline__ cx<double> phase_product(cx<double> a, cx<double> b) { return a * b; }
+__device__ __forceinline__ cx<float> phase_product(cx<float> a, cx<float> b)
+{
+    return a + b + a * b;
+}
+
 // The half-step factor exp(-i V_eff(r_m) dt/2) of one time step is
 //   P_m exp(z r_m^2),   z = zr + i zi = -(dt/2) c (kappa + i gamma) T^3,
 // c = 1/2 (singlet) or 7/32 (octet), P_m the static phase (table row).  It is
 // applied as two diagonal factors: the real damping D_m = exp(zr r_m^2),
 // applied as u + (D_m - 1) u with D_m - 1 from expm1 so that its rounding is
 // relative to the (small) difference and does not bias the norm step after
-// step, and the phase C_m = P_m exp(i zi r_m^2), of modulus one.  The step is
+// step, and the phase C_m = P_m exp(i zi r_m^2), of modulus one (held as
+// C_m - 1 in FP32, apply_phase).  The step is
 //   D C [DST kin DST] C D,
 // the bracket and C are unitary.  FP32-bulk renormalises C [DST kin DST] C
-// as a whole to the norm it receives, which also absorbs the modulus error of
-// C_m in FP32.  FAST: every argument is small (|zr| r^2 <= 1/2, |zi| r^2 <=
+// as a whole to the norm it receives, which also absorbs what modulus error
+// of C_m remains in FP32.  FAST: every argument is small (|zr| r^2 <= 1/2, |zi| r^2 <=
 // pi/4 on the whole grid: a per-step, wave-uniform decision), so short
 // series suffice.
 template <class R, bool GAMMA, bool FAST>
@@ -182,9 +252,14 @@ struct HalfStep {
     {
         if constexpr (GAMMA) {
             R s, c;
-            if constexpr (FAST) sincos_small(zi * x2, &s, &c);
-            else qsincos(zi * x2, &s, &c);
-            return p * mk(c, s);
+            if constexpr (std::is_same<R, float>::value) {
+                if constexpr (FAST) sincos_small_m1(zi * x2, &s, &c);
+                else qsincos_m1(zi * x2, &s, &c);
+            } else {
+                if constexpr (FAST) sincos_small(zi * x2, &s, &c);
+                else qsincos(zi * x2, &s, &c);
+            }
+            return phase_product(p, mk(c, s));
         } else {
             return p;
         }
@@ -250,9 +325,14 @@ struct HalfStepKSU {
         const R vr = (kms <= vsb ? kms : vsb) + cent / (r * r);
         const R vi = -cI * phi(x);
         R s, c;
-        qsincos(-half_dt * vr, &s, &c);
         dm1 = m > 0 ? qexpm1(half_dt * vi) : R(0);
-        C = m > 0 ? mk(c, s) : mk(R(1), R(0));
+        if constexpr (std::is_same<R, float>::value) {
+            qsincos_m1(-half_dt * vr, &s, &c);       // c = cos - 1
+            C = m > 0 ? mk(c, s) : mk(R(0), R(0));
+        } else {
+            qsincos(-half_dt * vr, &s, &c);
+            C = m > 0 ? mk(c, s) : mk(R(1), R(0));
+        }
     }
 };
 
@@ -324,7 +404,7 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
         }
         const cx<R> w = u + scale(u, dm[E]);
         if constexpr (SUM) acc += abs2d(w);
-        u = C * w;
+        u = apply_phase(w, C);
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
         apply(ln.ja + Rr * T, a[Rr], std::integral_constant<int, Rr>{});
@@ -351,7 +431,7 @@ __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
             R unused;
             h.factors(m, h.preload(m), unused, C);
         }
-        const cx<R> w = C * u;
+        const cx<R> w = apply_phase(u, C);
         if constexpr (SUM0) x0 += abs2d(w);
         u = w + scale(w, dm[E]);
         x1 += abs2d(u);
@@ -397,6 +477,19 @@ __device__ __forceinline__ double sum_abs2(const cx<R>* a, const cx<R>* b)
     double acc = 0.0;
     sfor<0, R1>([&](auto Rr) QT_INL { acc += abs2d(a[Rr]) + abs2d(b[Rr]); });
     return acc;
+}
+
+// Entry e (the e-th jump, 0-based) of trajectory idx's jump log: the step
+// after which it happened and the new (l, colour).  Lane 0 writes.
+__device__ __forceinline__ void log_jump(const qt_results& o, int64_t idx, int e, int64_t n, int l,
+                                         int c)
+{
+    if (o.jump_log != nullptr && e < o.jump_log_cap && threadIdx.x == 0) {
+        int32_t* d = o.jump_log + 3 * ((size_t)idx * o.jump_log_cap + e);
+        d[0] = (int32_t)n;
+        d[1] = l;
+        d[2] = c;
+    }
 }
 
 // Writes the results of a finished trajectory (overlaps in FP64).
@@ -712,6 +805,7 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
                 const double ul = uniform01(e.w[0]), uc = uniform01(e.w[1]);
                 l = (ul < (double)l / (double)(2 * l + 1)) ? l - 1 : l + 1;
                 c = (c == QT_OCTET) ? (uc < 2.0 / 7.0 ? QT_SINGLET : QT_OCTET) : QT_OCTET;
+                log_jump(g.out, idx, n_jumps, n, l, c);
                 sfor<0, R1>([&](auto Rr) QT_INL {
                     a[Rr] = scale(a[Rr], R(ls.ja + Rr * T) * dr);
                     b[Rr] = scale(b[Rr], R(ls.jb + Rr * T) * dr);

@@ -88,7 +88,8 @@ struct qt_job {
     int grid = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;   // by launches per replay
+    // by (full segments, remaining steps) per replay
+    std::map<std::pair<int64_t, int64_t>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     FusedArgs args{};
     fused_launcher launch = nullptr;
 };
@@ -177,23 +178,28 @@ qt_status qt_job_advance(qt_job* j, int64_t steps, void* hip_stream)
     if (steps == 0 || j->n_traj == 0) return QT_OK;
     std::lock_guard<std::mutex> lk(j->ctx->mu);
     QT_HIP(hipSetDevice(j->ctx->device));
-    const int64_t launches = (steps + j->seg_steps - 1) / j->seg_steps;
-    auto it = j->graphs.find(launches);
+    // `steps` steps exactly: full segments, then one launch of the remainder
+    const int64_t full = steps / j->seg_steps, rem = steps % j->seg_steps;
+    const int64_t launches = full + (rem > 0 ? 1 : 0);
+    const auto key = std::make_pair(full, rem);
+    auto it = j->graphs.find(key);
     if (it == j->graphs.end()) {
-        // capture `launches` segment launches once, replay afterwards
+        // capture the launches once, replay afterwards
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         QT_HIP(hipStreamBeginCapture(j->stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
+        FusedArgs last = j->args;
+        last.seg_steps = rem;
         for (int64_t k = 0; k < launches && e == hipSuccess; ++k) {
             e = launch_queue_reset(j->queue, j->stream);
-            if (e == hipSuccess) e = j->launch(j->args, j->grid, j->stream);
+            if (e == hipSuccess) e = j->launch(k < full ? j->args : last, j->grid, j->stream);
         }
         hipError_t e2 = hipStreamEndCapture(j->stream, &g);
         if (e != hipSuccess) return fail(QT_EDEVICE, "capture failed: %s", hipGetErrorString(e));
         if (e2 != hipSuccess) return fail(QT_EDEVICE, "end capture failed: %s", hipGetErrorString(e2));
         QT_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-        it = j->graphs.emplace(launches, std::make_pair(g, ge)).first;
+        it = j->graphs.emplace(key, std::make_pair(g, ge)).first;
     }
     hipStream_t us = static_cast<hipStream_t>(hip_stream);
     QT_HIP(hipEventRecord(j->ev_in, us));
@@ -270,6 +276,7 @@ qt_status qt_job_load(qt_job* j, const void* src, void* hip_stream)
 qt_status qt_job_results(qt_job* j, const qt_results* dev_out, void* hip_stream)
 {
     if (!j || !dev_out) return fail(QT_EINVAL, "null argument");
+    if (dev_out->jump_log) return fail(QT_EINVAL, "a job keeps no jump log");
     QT_HIP(hipSetDevice(j->ctx->device));
     hipStream_t us = static_cast<hipStream_t>(hip_stream);
     QT_HIP(hipEventRecord(j->ev_in, j->stream));

@@ -251,6 +251,7 @@ __global__ __launch_bounds__(W) void plain_norm_jump_kernel(const GroupDesc* gp,
                 const double ul = uniform01(e.w[0]), uc = uniform01(e.w[1]);
                 s.l = (ul < (double)s.l / (double)(2 * s.l + 1)) ? s.l - 1 : s.l + 1;
                 s.c = (s.c == QT_OCTET) ? (uc < 2.0 / 7.0 ? QT_SINGLET : QT_OCTET) : QT_OCTET;
+                log_jump(g.out, tr, s.n_jumps, n, s.l, s.c);
                 double acc = 0.0;
                 for (int m = threadIdx.x; m < N; m += W) {
                     const double rm = (double)m * g.dr;

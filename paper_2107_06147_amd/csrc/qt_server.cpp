@@ -9,8 +9,10 @@
 // their results are copied to host memory, their device memory is freed and
 // their latency (completion - submission) is recorded.  A trajectory's
 // result depends only on its own inputs and ids and on the kernel variant,
-// which is fixed per (N, precision) for the life of the server, so a request
-// gives bitwise the same result alone or in a mix.
+// which the server fixes per (N, potential) at its first use and keeps for
+// its life (later qt_plan calls on the context do not change it), so a
+// request gives bitwise the same result alone or in a mix.  A request whose
+// admission or result copy fails ends with that failure's status.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,7 +32,7 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-enum ReqState { QUEUED, RUNNING, DONE, CANCELED };
+enum ReqState { QUEUED, RUNNING, DONE, CANCELED, FAILED };
 
 struct Request {
     uint64_t id = 0;
@@ -48,7 +50,16 @@ struct Request {
     std::vector<double> norm, first_r, overlap, survival, mean_r, min_gap;
     std::vector<int32_t> l, color, n_jumps, status;
     std::vector<int64_t> steps_done;
-    std::vector<double> psi;
+    std::vector<char> psi_raw;    // final wave functions, kernel precision
+    // FAILED: the status and message of the failure
+    qt_status fail_status = QT_OK;
+    std::string fail_msg;
+};
+
+// The kernel variant of one (N, potential) class, fixed at its first use.
+struct Variant {
+    int W = 0, slots = 0;
+    fused_launcher launch = nullptr;
 };
 
 }  // namespace
@@ -72,6 +83,7 @@ struct qt_server {
     int64_t completed = 0, admitted = 0, traj_steps = 0;
     double busy_s = 0.0;
     std::string error;
+    std::map<int, Variant> variants;   // by 2 N + potential
 };
 
 namespace {
@@ -90,8 +102,12 @@ qt_status admit(qt_server* s, Request& q)
     const int64_t n = std::max<int64_t>(q.hb.batch.n_traj, 1);
     qt_status st = alloc_results(q.hb.batch.n_traj, &q.res);
     if (st != QT_OK) return st;
-    QT_HIP(hipMalloc(reinterpret_cast<void**>(&q.st), n * sizeof(TrajState)));
-    QT_HIP(hipMalloc(&q.st_psi, (size_t)n * q.hb.phys.N * elem_bytes(prec)));
+    if (hipMalloc(reinterpret_cast<void**>(&q.st), n * sizeof(TrajState)) != hipSuccess ||
+        hipMalloc(&q.st_psi, (size_t)n * q.hb.phys.N * elem_bytes(prec)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(QT_ENOMEM, "no device memory for the state of %lld trajectories",
+                    (long long)n);
+    }
     QT_HIP(hipMemsetAsync(q.st, 0, n * sizeof(TrajState), s->stream));
     std::vector<const HostBatch*> hbv{&q.hb};
     std::vector<qt_results> outs{q.res.r};
@@ -118,6 +134,14 @@ void release(Request& q)
     q.st_psi = q.dg.mem = nullptr;
 }
 
+// Marks q failed with the calling thread's last error (the caller holds s->mu).
+void mark_failed(Request& q, qt_status st)
+{
+    q.state = FAILED;
+    q.fail_status = st;
+    q.fail_msg = qt_last_error();
+}
+
 qt_status fetch_results(qt_server* s, Request& q)
 {
     const int64_t n = q.hb.batch.n_traj;
@@ -131,16 +155,12 @@ qt_status fetch_results(qt_server* s, Request& q)
     h.status = q.status.data(); h.steps_done = q.steps_done.data();
     qt_status st = copy_results(q.res.r, h, n, hipMemcpyDeviceToHost, s->stream);
     if (st != QT_OK) return st;
-    // final wave functions (kept in the checkpoint buffer) as FP64
-    q.psi.resize((size_t)2 * n * q.hb.phys.N);
-    if (n) {
-        double* tmp = nullptr;
-        QT_HIP(hipMalloc(reinterpret_cast<void**>(&tmp), q.psi.size() * 8));
-        QT_HIP(launch_widen(q.st_psi, s->cfg.precision, tmp, n * q.hb.phys.N, s->stream));
-        QT_HIP(hipMemcpyAsync(q.psi.data(), tmp, q.psi.size() * 8, hipMemcpyDeviceToHost, s->stream));
-        QT_HIP(hipStreamSynchronize(s->stream));
-        hipFree(tmp);
-    }
+    // final wave functions (kept in the checkpoint buffer) in the kernel's
+    // precision; widened to FP64 on the host by qt_wait when asked for
+    q.psi_raw.resize((size_t)n * q.hb.phys.N * elem_bytes(s->cfg.precision));
+    if (n)
+        QT_HIP(hipMemcpyAsync(q.psi_raw.data(), q.st_psi, q.psi_raw.size(), hipMemcpyDeviceToHost,
+                              s->stream));
     QT_HIP(hipStreamSynchronize(s->stream));
     return QT_OK;
 }
@@ -198,15 +218,18 @@ qt_status run_round(qt_server* s, int64_t* advanced)
     for (size_t c = 0; c < Ns.size(); ++c) {
         if (!count[c]) continue;
         const int N = Ns[c] / 2, pot = Ns[c] % 2;
-        int W = 0, slots = 0;
-        fused_launcher launch = nullptr;
         qt_context::Tables t;
         qt_status st;
+        Variant& v = s->variants[Ns[c]];
         {
             std::lock_guard<std::mutex> lk(s->ctx->mu);
-            if ((st = pick_launcher(s->ctx, prec, N, pot, &W, &launch, &slots)) != QT_OK) return st;
+            if (!v.launch &&
+                (st = pick_launcher(s->ctx, prec, N, pot, &v.W, &v.launch, &v.slots)) != QT_OK)
+                return st;
             if ((st = ensure_tables(s->ctx, prec, N, &t)) != QT_OK) return st;
         }
+        const fused_launcher launch = v.launch;
+        const int slots = v.slots;
         FusedArgs a;
         a.groups = dgroups;
         a.item_group = ig + start[c];
@@ -269,10 +292,11 @@ void server_loop(qt_server* s)
                 if (!s->running.empty() && s->in_use + b > s->budget) break;
                 s->queue.pop_front();
                 q->bytes = b;
-                if (admit(s, *q) != QT_OK) {
-                    s->error = qt_last_error();
+                const qt_status ast = admit(s, *q);
+                if (ast != QT_OK) {
+                    // this request fails with the cause; the others go on
+                    mark_failed(*q, ast);
                     release(*q);
-                    q->state = CANCELED;
                     continue;
                 }
                 s->in_use += b;
@@ -289,10 +313,11 @@ void server_loop(qt_server* s)
         std::lock_guard<std::mutex> lk(s->mu);
         s->busy_s += dt;
         if (st != QT_OK) {
+            // a failed round: every running request ends with its cause
             s->error = qt_last_error();
             for (auto& q : s->running) {
                 release(*q);
-                q->state = CANCELED;
+                mark_failed(*q, st);
             }
             s->running.clear();
             s->in_use = 0;
@@ -313,7 +338,8 @@ void server_loop(qt_server* s)
             delta += cur - last_steps[q->id];
             last_steps[q->id] = cur;
             if (q->state == DONE) {
-                fetch_results(s, *q);
+                const qt_status fst = fetch_results(s, *q);
+                if (fst != QT_OK) mark_failed(*q, fst);
                 release(*q);
                 s->in_use -= q->bytes;
                 q->t_done = Clock::now();
@@ -388,18 +414,20 @@ qt_status qt_poll(qt_server* s, uint64_t id, int32_t* done)
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->all.find(id);
     if (it == s->all.end()) return fail(QT_ENOTFOUND, "unknown request %llu", (unsigned long long)id);
-    *done = it->second->state == DONE || it->second->state == CANCELED;
+    const ReqState rs = it->second->state;
+    *done = rs == DONE || rs == CANCELED || rs == FAILED;
     return QT_OK;
 }
 
 qt_status qt_wait(qt_server* s, uint64_t id, const qt_results* host_out, double timeout_s)
 {
     if (!s) return fail(QT_EINVAL, "null argument");
+    if (host_out && host_out->jump_log) return fail(QT_EINVAL, "the server keeps no jump log");
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->all.find(id);
     if (it == s->all.end()) return fail(QT_ENOTFOUND, "unknown request %llu", (unsigned long long)id);
     auto q = it->second;
-    auto pred = [&] { return q->state == DONE || q->state == CANCELED; };
+    auto pred = [&] { return q->state == DONE || q->state == CANCELED || q->state == FAILED; };
     if (timeout_s < 0) {
         s->cv_done.wait(lk, pred);
     } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) {
@@ -407,8 +435,13 @@ qt_status qt_wait(qt_server* s, uint64_t id, const qt_results* host_out, double 
     }
     if (q->state == CANCELED) {
         s->all.erase(id);
-        return fail(QT_ECANCELED, "request %llu was cancelled%s%s", (unsigned long long)id,
-                    s->error.empty() ? "" : ": ", s->error.c_str());
+        return fail(QT_ECANCELED, "request %llu was cancelled", (unsigned long long)id);
+    }
+    if (q->state == FAILED) {
+        const qt_status st = q->fail_status;
+        const std::string msg = q->fail_msg;
+        s->all.erase(id);
+        return fail(st, "request %llu failed: %s", (unsigned long long)id, msg.c_str());
     }
     if (host_out) {
         const size_t n = q->norm.size();
@@ -424,7 +457,15 @@ qt_status qt_wait(qt_server* s, uint64_t id, const qt_results* host_out, double 
         cp(host_out->n_jumps, q->n_jumps.data(), n * 4);
         cp(host_out->status, q->status.data(), n * 4);
         cp(host_out->steps_done, q->steps_done.data(), n * 8);
-        cp(host_out->psi, q->psi.data(), q->psi.size() * 8);
+        if (host_out->psi) {
+            const size_t cnt = (size_t)n * q->hb.phys.N;
+            if (s->cfg.precision == QT_FP64) {
+                cp(host_out->psi, q->psi_raw.data(), cnt * 16);
+            } else {
+                const float* f = reinterpret_cast<const float*>(q->psi_raw.data());
+                for (size_t k = 0; k < 2 * cnt; ++k) host_out->psi[k] = (double)f[k];
+            }
+        }
     }
     s->all.erase(id);
     return QT_OK;

@@ -62,7 +62,8 @@ class qt_batch(C.Structure):
 class qt_results(C.Structure):
     _fields_ = [("norm", _D), ("first_r", _D), ("overlap", _D), ("survival", _D),
                 ("mean_r", _D), ("l", _I32), ("color", _I32), ("n_jumps", _I32),
-                ("status", _I32), ("steps_done", _I64), ("min_gap", _D), ("psi", _D)]
+                ("status", _I32), ("steps_done", _I64), ("min_gap", _D), ("psi", _D),
+                ("jump_log", _I32), ("jump_log_cap", C.c_int32), ("pad0", C.c_int32)]
 
 
 class qt_server_cfg(C.Structure):
@@ -190,8 +191,10 @@ def batch(cfg, precision, form=QT_FORM_FUSED, n_traj=None, traj_id0=None):
                     int(cfg.get("no_jump_shortcut", 0)))
 
 
-def alloc_results(n, N, want_psi, device="cuda"):
-    """Output tensors on the GPU (torch) and the qt_results of their pointers."""
+def alloc_results(n, N, want_psi, device="cuda", jump_log_cap=0):
+    """Output tensors on the GPU (torch) and the qt_results of their pointers.
+    jump_log_cap > 0 adds a jump log of that many (step, l, colour) entries
+    per trajectory, filled with -1 where no jump was logged."""
     import torch
     f64 = dict(dtype=torch.float64, device=device)
     out = {
@@ -207,6 +210,8 @@ def alloc_results(n, N, want_psi, device="cuda"):
     }
     if want_psi:
         out["psi"] = torch.zeros(n, N, 2, **f64)
+    if jump_log_cap > 0:
+        out["jump_log"] = torch.full((n, int(jump_log_cap), 3), -1, dtype=torch.int32, device=device)
     return out, results_struct(out)
 
 
@@ -217,20 +222,24 @@ def results_struct(out, row=0):
         if t is None:
             return None
         return C.cast(C.c_void_p(t.data_ptr() + row * t.stride(0) * t.element_size()), typ)
+    jl = out.get("jump_log")
     return qt_results(p("norm", _D), p("first_r", _D), p("overlap", _D), p("survival", _D),
                       p("mean_r", _D), p("l", _I32), p("color", _I32), p("n_jumps", _I32),
-                      p("status", _I32), p("steps_done", _I64), p("min_gap", _D), p("psi", _D))
+                      p("status", _I32), p("steps_done", _I64), p("min_gap", _D), p("psi", _D),
+                      p("jump_log", _I32), 0 if jl is None else int(jl.shape[1]), 0)
 
 
-_RESULT_FIELDS = [f for f, _ in qt_results._fields_]
+# the pointer fields of qt_results (all but the trailing jump_log_cap, pad0)
+_RESULT_FIELDS = [f for f, _ in qt_results._fields_][:-2]
 
 
 def results_array(out, rows, keep):
     """qt_results of the tensors in `out` for every start row in `rows` at
     once (ctypes array; its pointer table is a numpy array kept in `keep`)."""
     rows = np.asarray(rows, dtype=np.int64)
-    base = np.zeros(len(_RESULT_FIELDS), dtype=np.int64)
-    step = np.zeros(len(_RESULT_FIELDS), dtype=np.int64)
+    nf = len(_RESULT_FIELDS)
+    base = np.zeros(nf + 1, dtype=np.int64)     # + the (jump_log_cap, pad0) word
+    step = np.zeros(nf + 1, dtype=np.int64)
     for j, name in enumerate(_RESULT_FIELDS):
         t = out.get(name)
         if t is not None:
@@ -238,6 +247,8 @@ def results_array(out, rows, keep):
             step[j] = t.stride(0) * t.element_size()
     tab = base[None, :] + rows[:, None] * step[None, :]
     tab[:, base == 0] = 0
+    jl = out.get("jump_log")
+    tab[:, nf] = 0 if jl is None else int(jl.shape[1])   # little-endian: cap, then pad 0
     tab = np.ascontiguousarray(tab.astype(np.uint64))
     keep.append(tab)
     return (qt_results * len(rows)).from_buffer(tab)
@@ -258,7 +269,7 @@ def host_results(n, N, want_psi):
                       out[k].ctypes.data_as(_I32 if out[k].dtype == np.int32 else _I64))
                      for k in ("norm", "first_r", "overlap", "survival", "mean_r", "l", "color",
                                "n_jumps", "status", "steps_done", "min_gap")],
-                   _dp(out.get("psi")))
+                   _dp(out.get("psi")), None, 0, 0)
     return out, r
 
 
@@ -357,12 +368,12 @@ def _stream_handle(stream):
 
 
 def run(ctx, cfg, precision=QT_FP64, form=QT_FORM_FUSED, want_psi=False, n_traj=None,
-        traj_id0=None, stream=None, out=None):
+        traj_id0=None, stream=None, out=None, jump_log_cap=0):
     """qt_run on a config dict; returns the dict of output tensors."""
     keep = []
     n = int(cfg["n_traj"] if n_traj is None else n_traj)
     if out is None:
-        out, res = alloc_results(n, int(cfg["N"]), want_psi)
+        out, res = alloc_results(n, int(cfg["N"]), want_psi, jump_log_cap=jump_log_cap)
     else:
         res = results_struct(out)
     p = physics(cfg)

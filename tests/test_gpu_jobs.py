@@ -74,6 +74,46 @@ def test_graph_replay_and_checkpoint_resume(ctx):
     _same(ref, out)
 
 
+def _job_steps(job, n):
+    """(step, done) of every trajectory, read from a host checkpoint (the
+    88-byte state records lead the blob: step int64 at offset 0, done int32
+    at offset 28)."""
+    import torch
+    blob = torch.empty(job.state_bytes(), dtype=torch.uint8)
+    job.save(blob.data_ptr())
+    torch.cuda.synchronize()
+    rec = blob.numpy()[:88 * n].reshape(n, 88)
+    return rec[:, 0:8].copy().view(np.int64)[:, 0], rec[:, 28:32].copy().view(np.int32)[:, 0]
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_advance_takes_exactly_the_steps_asked(ctx, prec):
+    """advance(50) with segments of 37 steps runs 50 steps (a segment of 37,
+    then one of 13), advance(10) with segments of 1000 runs 10; every
+    unfinished trajectory's checkpoint is at that step, and the finished
+    run equals a single one."""
+    import torch
+    cfg = dict(_cfg(512, 300), kappa_hat=2.0)
+    ref = gpu_run(ctx, cfg, prec)
+    job = qt.Job(ctx, cfg, precision=prec, segment_steps=37)
+    job.advance(50)
+    step, done = _job_steps(job, cfg["n_traj"])
+    assert np.all(step[done == 0] == 50) and (done == 0).sum() > 0
+    job.advance(50)                            # the same graph again
+    step, done = _job_steps(job, cfg["n_traj"])
+    assert np.all(step[done == 0] == 100)
+    job.advance(200)
+    assert job.done()
+    _same(ref, qt.to_numpy(job.results(want_psi=True)))
+    torch.cuda.synchronize()
+    job.close()
+    job = qt.Job(ctx, cfg, precision=prec, segment_steps=1000)
+    job.advance(10)
+    step, done = _job_steps(job, cfg["n_traj"])
+    assert np.all(step[done == 0] == 10)
+    job.close()
+
+
 def test_job_fp64_matches_oracle(ctx):
     import torch
     cfg = _cfg()
@@ -140,7 +180,8 @@ def _requests():
 
 
 def test_server_alone_vs_mix_bitwise(ctx):
-    """Each request's result in the concurrent mix equals its result alone."""
+    """Each request's result in the concurrent mix equals its result alone,
+    bit for bit, and the oracle's within the FP32-bulk bounds."""
     reqs = _requests()
     alone = [gpu_run(ctx, c, F32) for c in reqs]
     srv = qt.Server(ctx, precision=F32, segment_steps=64)
@@ -152,6 +193,25 @@ def test_server_alone_vs_mix_bitwise(ctx):
         _same(a, o)
     assert st["completed"] == 3 and st["p99_latency_s"] >= st["p50_latency_s"] > 0
     assert st["traj_steps"] == sum(int(a["steps_done"].sum()) for a in alone)
+    for c, o in zip(reqs, outs):
+        print("server vs oracle", c["N"], compare(oracle.run(c, want_psi=True), o, F32,
+                                                  label="server N=%d" % c["N"]))
+
+
+def test_server_admission_failure_has_its_own_status(ctx):
+    """A request that passes the budget but whose state does not fit the
+    device (655 GB of wave functions) fails at admission with QT_ENOMEM, not
+    as a cancellation; the server goes on with the next request."""
+    srv = qt.Server(ctx, precision=F32, segment_steps=50, hbm_budget_bytes=1 << 50)
+    big = dict(_requests()[0], N=8192, L=160.0, n_traj=10_000_000, max_steps=10)
+    rid = srv.submit(big)
+    with pytest.raises(qt.QtError) as e:
+        srv.wait(rid, timeout_s=120)
+    assert e.value.status == qt.QT_ENOMEM
+    good = _requests()[0]
+    out = srv.wait(srv.submit(good), timeout_s=120)
+    assert np.all(out["steps_done"] == 200)
+    srv.close()
 
 
 def test_server_rejects_bad_requests_and_keeps_running(ctx):
