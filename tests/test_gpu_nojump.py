@@ -54,12 +54,7 @@ def test_shortcut_against_oracle(ctx, prec):
     cfg = dict(_cfg(n_traj=24), no_jump_shortcut=1)
     ref = oracle.run(cfg, want_psi=True)
     out = gpu_run(ctx, cfg, prec)
-    # FP32: trajectory 1 makes its fourth jump (to l = 4) on the very last
-    # step, which multiplies the FP32 rounding floor far from the origin by
-    # r just before the comparison: 2.3e-5 against 1.8e-6 for the no-jump
-    # trajectories and 3-6e-6 for one to three jumps earlier in the run
-    err = compare(ref, out, prec, label="shortcut",
-                  tol=dict(psi=3e-5) if prec == F32 else None)
+    err = compare(ref, out, prec, label="shortcut")
     print("shortcut parity", prec, err)
     # the shortcut decision compares the threshold with the zeroth's
     # smallest norm; away from that norm both sides decide alike
