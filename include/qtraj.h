@@ -321,6 +321,28 @@ qt_status qt_plan_set(qt_context* ctx, int32_t N, int32_t precision, int32_t thr
 qt_status qt_eigen_basis(qt_context* ctx, const qt_physics* phys, double* energies,
                          double* basis);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): qt_run of
+ * the FUSED form without any device allocation.  Its per-call device data
+ * (queue counter, work items, the batch's descriptor and tables) goes into
+ * one static device buffer of QT_NOALLOC_BUFFER_BYTES that each device
+ * holds for the life of the process.  Every call on a device shares that
+ * buffer, so calls that overlap on one device race: issue them on one
+ * stream, or otherwise one after another.  The context's cached device
+ * tables of the grid must exist already, built by an earlier qt_run (or
+ * qt_eigen_basis) on the same context with the same N, precision, L, mass,
+ * alpha_s, dt and potential: a call that would have to build one returns
+ * QT_EINVAL instead.  Also QT_EINVAL: the PLAIN form, no_jump_shortcut,
+ * vacuum_steps > 0, or a batch whose items and tables exceed the buffer
+ * (12 bytes per trajectory plus about 48 N + 16 n_tab bytes of tables:
+ * about 1.3 million trajectories at N = 2048).  Results, status and timing
+ * as qt_run; stream-ordered on hip_stream (the staging copy of the host
+ * tables synchronises it). */
+#define QT_NOALLOC_BUFFER_BYTES (16u << 20)
+qt_status qt_run_noalloc(qt_context* ctx, const qt_physics* phys, const qt_ttable* tt,
+                         const qt_init* init, const qt_batch* batch, const qt_results* dev_out,
+                         void* hip_stream);
+
 const char* qt_last_error(void);
 const char* qt_version(void);
 

@@ -28,6 +28,10 @@ constexpr double kPi = 3.14159265358979323846;
 }  // namespace
 
 namespace qt {
+thread_local bool g_no_alloc = false;
+}  // namespace qt
+
+namespace qt {
 
 qt_status fail(qt_status s, const char* fmt, ...)
 {
@@ -407,6 +411,9 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
         *out = it->second;
         return QT_OK;
     }
+    if (g_no_alloc)
+        return fail(QT_EINVAL, "no transform tables for N=%d precision=%d on this context yet: "
+                    "run qt_run with this grid first", N, prec);
     const bool f32 = prec == QT_FP32_BULK;
     // FFT twiddles exp(-2 pi i m/n) and DST-I pre-processing weights
     // ((s + 1/2)/2, (s - 1/2)/2), s = sin(pi m/n), of a transform of length n
@@ -538,6 +545,8 @@ qt_status ensure_ksu_table(qt_context* ctx, int prec, const void** out)
         *out = it->second;
         return QT_OK;
     }
+    if (g_no_alloc)
+        return fail(QT_EINVAL, "no KSU table on this context yet: run qt_run with it first");
     const int nf = 4097, nc = 16257;
     std::vector<double> v(2 * (size_t)(nf + nc));
     for (int k = 0; k < nf; ++k) ksu_phi_and_slope(k / 8192.0, &v[2 * k], &v[2 * k + 1]);
@@ -610,6 +619,9 @@ qt_status ensure_phase(qt_context* ctx, const HostBatch& h, int prec, const void
         *out = it->second;
         return QT_OK;
     }
+    if (g_no_alloc)
+        return fail(QT_EINVAL, "no static phase table for this grid (N, L, mass, alpha_s, dt) "
+                    "and precision on this context yet: run qt_run with it first");
     const size_t bytes = (size_t)2 * (kLTab + 1) * h.phys.N * elem_bytes(prec);
     std::vector<char> tab(bytes);
     phase_table(h, prec == QT_FP32_BULK, tab.data());
@@ -623,7 +635,7 @@ qt_status ensure_phase(qt_context* ctx, const HostBatch& h, int prec, const void
 
 qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb, int prec,
                         const std::vector<qt_results>& outs, bool with_Tn, hipStream_t s,
-                        bool async_alloc, DeviceGroups* dg)
+                        bool async_alloc, DeviceGroups* dg, void* into, size_t into_cap)
 {
     const bool f32 = prec == QT_FP32_BULK;
     const size_t ng = hb.size();
@@ -666,7 +678,12 @@ qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb
         if (st != QT_OK) return st;
     }
     dg->bytes = off;
-    if (async_alloc) {
+    if (into) {
+        if (off > into_cap)
+            return fail(QT_EINVAL, "the batch's tables need %zu bytes, more than the %zu left in "
+                        "the static buffer", off, into_cap);
+        dg->mem = into;
+    } else if (async_alloc) {
         QT_HIP(hipMallocAsync(&dg->mem, off, s));
     } else {
         QT_HIP(hipMalloc(&dg->mem, off));
@@ -828,6 +845,11 @@ qt_status qt_context_create(int device, qt_context** out)
     auto* c = new qt_context();
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
+    size_t nab = 0;
+    if (qt_status st = noalloc_buffer(device, &c->noalloc_buf, &nab); st != QT_OK) {
+        delete c;
+        return st;
+    }
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         delete c;
         return fail(QT_EDEVICE, "hipEventCreate failed");

@@ -378,6 +378,9 @@ qt_status eigen_states(qt_context* ctx, const qt_physics* p, qt_context::Eigen* 
         *out = it->second;
         return QT_OK;
     }
+    if (g_no_alloc)
+        return fail(QT_EINVAL, "vacuum eigenstates for this grid not computed on this context "
+                    "yet: call qt_eigen_basis or qt_run with them first");
     QT_HIP(hipSetDevice(ctx->device));
     qt_context::Eigen e;
     auto b = std::make_shared<std::vector<double>>(6 * (size_t)p->N, 0.0);

@@ -37,11 +37,21 @@ struct qt_context {
         std::shared_ptr<const std::vector<double>> basis;   // 6 N
     };
     std::map<std::vector<double>, Eigen> eigen;
+    // this device's copy of the library's static no-allocation buffer
+    // (qt_run_noalloc), looked up when the context is created
+    void* noalloc_buf = nullptr;
 };
 
 namespace qt {
 
 qt_status fail(qt_status s, const char* fmt, ...);
+
+// Set while the calling thread runs qt_run_noalloc: a context table, basis or
+// plan that would have to be built (device allocation) is an error instead.
+extern thread_local bool g_no_alloc;
+// The device address of the static no-allocation buffer on `device` (looked
+// up once per device, with the device current) and its size.
+qt_status noalloc_buffer(int device, void** ptr, size_t* bytes);
 #define QT_HIP(x)                                                                         \
     do {                                                                                  \
         hipError_t e_ = (x);                                                              \
@@ -102,9 +112,12 @@ struct DeviceGroups {
     GroupDesc* groups = nullptr;     // device
     std::vector<GroupDesc> host;     // host copy
 };
+// `into` (optional): device memory of `into_cap` bytes to build the image in
+// instead of an allocation (QT_EINVAL when it does not fit).
 qt_status upload_groups(qt_context* ctx, const std::vector<const HostBatch*>& hb, int prec,
                         const std::vector<qt_results>& outs, bool with_Tn,
-                        hipStream_t s, bool async_alloc, DeviceGroups* out);
+                        hipStream_t s, bool async_alloc, DeviceGroups* out,
+                        void* into = nullptr, size_t into_cap = 0);
 qt_status ensure_phase(qt_context* ctx, const HostBatch& hb, int prec, const void** out);
 qt_status ensure_ksu_table(qt_context* ctx, int prec, const void** out);
 

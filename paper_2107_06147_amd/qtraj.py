@@ -85,6 +85,9 @@ _SIGS = {
     "qt_context_destroy": (C.c_int, [_VP]),
     "qt_run": (C.c_int, [_VP, C.POINTER(qt_physics), C.POINTER(qt_ttable), C.POINTER(qt_init),
                          C.POINTER(qt_batch), C.POINTER(qt_results), _VP]),
+    "qt_run_noalloc": (C.c_int, [_VP, C.POINTER(qt_physics), C.POINTER(qt_ttable),
+                                 C.POINTER(qt_init), C.POINTER(qt_batch), C.POINTER(qt_results),
+                                 _VP]),
     "qt_run_many": (C.c_int, [_VP, C.c_int32, C.POINTER(qt_physics), C.POINTER(qt_ttable),
                               C.POINTER(qt_init), C.POINTER(qt_batch), C.POINTER(qt_results), _VP]),
     "qt_job_create": (C.c_int, [_VP, C.POINTER(qt_physics), C.POINTER(qt_ttable),
@@ -382,6 +385,25 @@ def run(ctx, cfg, precision=QT_FP64, form=QT_FORM_FUSED, want_psi=False, n_traj=
     b = batch(cfg, precision, form, n, traj_id0)
     check(lib().qt_run(ctx.h, C.byref(p), C.byref(tt), C.byref(ini), C.byref(b), C.byref(res),
                        _stream_handle(stream)), "qt_run")
+    return out
+
+
+def run_noalloc(ctx, cfg, precision=QT_FP64, want_psi=False, n_traj=None, traj_id0=None,
+                stream=None, out=None):
+    """qt_run_noalloc (the fused form without device allocation) on a config
+    dict; `out`: result tensors of an earlier call to reuse."""
+    keep = []
+    n = int(cfg["n_traj"] if n_traj is None else n_traj)
+    if out is None:
+        out, res = alloc_results(n, int(cfg["N"]), want_psi)
+    else:
+        res = results_struct(out)
+    p = physics(cfg)
+    tt = ttable(cfg, keep)
+    ini = init(cfg, keep)
+    b = batch(cfg, precision, QT_FORM_FUSED, n, traj_id0)
+    check(lib().qt_run_noalloc(ctx.h, C.byref(p), C.byref(tt), C.byref(ini), C.byref(b),
+                               C.byref(res), _stream_handle(stream)), "qt_run_noalloc")
     return out
 
 
