@@ -2,7 +2,7 @@
 
 Workload (one "step" of this benchmark = one full batch): 4096 trajectories,
 N=2048, L=40 GeV^-1, dt=0.001 GeV^-1, Bjorken cooling 0.425 GeV at 0.6 fm/c
-down to 0.25 GeV (500-point table, 11,898 time steps per trajectory),
+down to 0.25 GeV (500-point table, 11,899 time steps per trajectory),
 Gaussian l=0 singlet of width 0.2 fm, jumps on; the timed steps cycle
 through (kappa_hat, gamma_hat) in {1,4} x {0,-2}.  Inputs are synthetic and
 generated in HBM-resident form before timing (the tables are uploaded inside
@@ -349,7 +349,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "4096 trajectories, N=2048, L=40, dt=0.001, Bjorken 0.425->0.25 GeV "
-                               "(11898 steps), Gaussian l=0 singlet 0.2 fm, jumps on, "
+                               "(11899 steps), Gaussian l=0 singlet 0.2 fm, jumps on, "
                                "kappa_hat in {1,4} x gamma_hat in {0,-2}",
                    "trajectories": n_traj, "grid_points": N, "time_steps": n_steps,
                    "form": "fused persistent, FP32 bulk + FP64 norm/threshold"},

@@ -18,7 +18,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qtraj_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# QTO_LIB: another build of the oracle (the mutation tests load deliberately
+# broken copies through it in child processes)
+_LIB_PATH = os.environ.get("QTO_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 SINGLET, OCTET = 0, 1

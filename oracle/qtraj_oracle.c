@@ -168,8 +168,11 @@ static void dst1_with_table(int32_t N, const double* tab, const double* in_re,
     out_im[0] = 0.0;
     for (int32_t k = 1; k < N; ++k) {
         double sr = 0.0, si = 0.0;
+        int32_t jk = 0;               /* (j k) mod 2N, stepped by k */
         for (int32_t j = 1; j < N; ++j) {
-            double s = tab[((int64_t)j * k) % (2 * N)];
+            jk += k;
+            if (jk >= 2 * N) jk -= 2 * N;
+            double s = tab[jk];
             sr += in_re[j] * s;
             si += in_im[j] * s;
         }
@@ -383,8 +386,8 @@ int qto_basis_state(int32_t N, double L, double mass, double alpha_s,
 /* ------------------------------------------------------------------------ */
 typedef struct {
     double* re; double* im;       /* u_j                                     */
-    double* tre; double* tim;     /* transform output                        */
-    double* kre; double* kim;     /* space kernel exp(-i V_eff dt/2)         */
+    double* tre; double* tim;     /* the state in sine-mode space            */
+    double* fre; double* fim;     /* half-step factor exp(-i V_eff dt/2)     */
 } workspace;
 
 static double norm_of(int32_t N, double dr, const double* re, const double* im)
@@ -394,48 +397,45 @@ static double norm_of(int32_t N, double dr, const double* re, const double* im)
     return dr * s;
 }
 
-/* loadSpaceKernel: exp(-i V_eff dt/2) = exp(V_I dt/2) exp(-i V_R dt/2). */
-static void load_space_kernel(const qto_physics* p, int32_t l, int32_t c, double T, workspace* w)
+/* The position-space factor of eq. (uUpdate), exp(-i V_eff dt/2) with
+ * V_eff = V_R + i V_I, at every grid point: its modulus exp(V_I dt/2) and
+ * its phase -V_R dt/2. */
+static void half_step_factor(const qto_physics* p, int32_t l, int32_t c, double T, workspace* w)
 {
     double dr = p->L / (double)p->N;
-    w->kre[0] = 0.0; w->kim[0] = 0.0;
+    w->fre[0] = 0.0; w->fim[0] = 0.0;
     for (int32_t j = 1; j < p->N; ++j) {
         double VR, VI;
         munich_potential(p, (double)j * dr, l, c, T, &VR, &VI);
-        double mag = exp(0.5 * p->dt * VI);
-        double ph = -0.5 * p->dt * VR;
-        w->kre[j] = mag * cos(ph);
-        w->kim[j] = mag * sin(ph);
+        double modulus = exp(0.5 * p->dt * VI);
+        double angle = -0.5 * p->dt * VR;
+        w->fre[j] = modulus * cos(angle);
+        w->fim[j] = modulus * sin(angle);
     }
 }
 
-static void mul_complex_inplace(int32_t N, double* re, double* im, const double* fre, const double* fim)
+/* a_j <- a_j f_j for complex a and f */
+static void pointwise_mul(int32_t N, double* are, double* aim, const double* fre, const double* fim)
 {
     for (int32_t j = 0; j < N; ++j) {
-        double a = re[j], b = im[j];
-        re[j] = a * fre[j] - b * fim[j];
-        im[j] = a * fim[j] + b * fre[j];
+        double x = are[j], y = aim[j];
+        are[j] = x * fre[j] - y * fim[j];
+        aim[j] = x * fim[j] + y * fre[j];
     }
 }
 
-/* makeStep: the five sub-steps of the Strang split, in the paper's order. */
-static void make_step(int32_t N, const double* tab, workspace* w,
-                      const double* mom_re, const double* mom_im)
+/* One time step, eq. (uUpdate): u <- F S E S F u, with F the half-step
+ * factor (w->f), S the sine transform of the grid (on the real and the
+ * imaginary part alike) and E = diag(exp(-i E_k dt)) the kinetic factor in
+ * sine-mode space.  S is applied out of place, from u into t and back. */
+static void strang_step(int32_t N, const double* sines, workspace* w,
+                        const double* ere, const double* eim)
 {
-    /* 1. half-step in configuration space */
-    mul_complex_inplace(N, w->re, w->im, w->kre, w->kim);
-    /* 2. sine transform of real and imaginary parts */
-    dst1_with_table(N, tab, w->re, w->im, w->tre, w->tim);
-    memcpy(w->re, w->tre, sizeof(double) * N);
-    memcpy(w->im, w->tim, sizeof(double) * N);
-    /* 3. full step in momentum space */
-    mul_complex_inplace(N, w->re, w->im, mom_re, mom_im);
-    /* 4. the DST-I is its own inverse */
-    dst1_with_table(N, tab, w->re, w->im, w->tre, w->tim);
-    memcpy(w->re, w->tre, sizeof(double) * N);
-    memcpy(w->im, w->tim, sizeof(double) * N);
-    /* 5. half-step in configuration space */
-    mul_complex_inplace(N, w->re, w->im, w->kre, w->kim);
+    pointwise_mul(N, w->re, w->im, w->fre, w->fim);
+    dst1_with_table(N, sines, w->re, w->im, w->tre, w->tim);
+    pointwise_mul(N, w->tre, w->tim, ere, eim);
+    dst1_with_table(N, sines, w->tre, w->tim, w->re, w->im);
+    pointwise_mul(N, w->re, w->im, w->fre, w->fim);
 }
 
 /* Singlet overlaps |<b|u>|^2 / <u|u> for the six basis states. */
@@ -570,8 +570,8 @@ static void run_one(const shared_setup* s, int64_t i, workspace* w, int zeroth)
     } else {
         for (int64_t n = 0; n < s->n_steps; ++n) {
             double T = qto_temperature(s->tt, s->tt->tau_start + (double)n * p->dt);
-            load_space_kernel(p, l, c, T, w);
-            make_step(N, s->tab, w, s->mom_re, s->mom_im);
+            half_step_factor(p, l, c, T, w);
+            strang_step(N, s->tab, w, s->mom_re, s->mom_im);
             norm = norm_of(N, dr, w->re, w->im);
             steps = n + 1;
             if (out->norm_trace) out->norm_trace[i * s->n_steps + n] = norm;
@@ -695,15 +695,15 @@ int qto_run(const qto_physics* p, const qto_ttable* tt, const qto_init* ini,
     double* buf0 = (double*)calloc((size_t)6 * N, sizeof(double));
     workspace w0;
     w0.re = buf0; w0.im = buf0 + N; w0.tre = buf0 + 2 * N; w0.tim = buf0 + 3 * N;
-    w0.kre = buf0 + 4 * N; w0.kim = buf0 + 5 * N;
+    w0.fre = buf0 + 4 * N; w0.fim = buf0 + 5 * N;
     /* in-vacuum evolution (T = 0) of the initial state, once, then stored as
        the state every trajectory starts from */
     if (tt->vacuum_steps > 0) {
         memcpy(w0.re, init_re, sizeof(double) * N);
         memcpy(w0.im, init_im, sizeof(double) * N);
         for (int64_t n = 0; n < tt->vacuum_steps; ++n) {
-            load_space_kernel(p, ini->l, ini->color, 0.0, &w0);
-            make_step(N, tab, &w0, mom_re, mom_im);
+            half_step_factor(p, ini->l, ini->color, 0.0, &w0);
+            strang_step(N, tab, &w0, mom_re, mom_im);
         }
         memcpy(init_re, w0.re, sizeof(double) * N);
         memcpy(init_im, w0.im, sizeof(double) * N);
@@ -741,7 +741,7 @@ int qto_run(const qto_physics* p, const qto_ttable* tt, const qto_init* ini,
         workspace w;
         double* buf = (double*)calloc((size_t)6 * N, sizeof(double));
         w.re = buf; w.im = buf + N; w.tre = buf + 2 * N; w.tim = buf + 3 * N;
-        w.kre = buf + 4 * N; w.kim = buf + 5 * N;
+        w.fre = buf + 4 * N; w.fim = buf + 5 * N;
 #pragma omp for schedule(dynamic, 1)
         for (int64_t i = 0; i < b->n_traj; ++i) run_one(&s, i, &w, 0);
         free(buf);

@@ -115,7 +115,7 @@ __global__ void plain_space_kernel(const GroupDesc* gp, double* psi, const TrajS
     if (tr >= n_traj || m == 0) return;
     const TrajState& s = st[tr];
     if (s.done) return;
-    // loadSpaceKernel(T_n): exp(-i V_eff dt/2) from the full potential
+    // the half-step factor exp(-i V_eff dt/2) at T_n from the full potential
     const double T = g.Tn[n];
     const double T3 = T * T * T;
     const double r = (double)m * g.dr;

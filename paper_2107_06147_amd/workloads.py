@@ -90,7 +90,7 @@ def c1_parity():
 
 def c2_headline(kappa_hat=4.0, gamma_hat=0.0, n_traj=4096, seed=1):
     """4096 trajectories, N=2048, L=40, dt=0.001, Bjorken 0.425 GeV at
-    0.6 fm/c down to 0.25 GeV (500 table points, 11,898 steps), Gaussian
+    0.6 fm/c down to 0.25 GeV (500 table points, 11,899 steps), Gaussian
     l=0 singlet of width 0.2 fm."""
     tau, T = bjorken_table(0.425, 0.6, 0.25, 500)
     return base(N=2048, L=40.0, dt=0.001, kappa_hat=kappa_hat, gamma_hat=gamma_hat,

@@ -276,6 +276,26 @@ def test_waiting_time_rule_and_renormalisation(oracle_lib):
         assert np.all(tr[start:] > r)
 
 
+def test_jump_multiplies_by_r_and_renormalises(oracle_lib):
+    """Sec. "Summary of QTraj execution", step 4: at a jump the state is
+    multiplied by the radial part of the collapse operator, r, and
+    renormalised.  The state right after the first jump equals r u / ||r u||
+    of the state the same evolution reaches without jumping at that step."""
+    cfg = W.base(N=256, L=20.0, dt=0.001, kappa_hat=20.0, init_kind=W.INIT_GAUSSIAN,
+                 init_width=1.0, n_traj=6, seed=3, **W.constant_T(0.5, 600))
+    res = oracle.run(cfg, jump_log_cap=4)
+    i = int(np.argmax(res["n_jumps"] > 0))
+    n = int(res["jump_log"][i, 0, 0])            # the step after which it jumped
+    one = dict(cfg, max_steps=n + 1)
+    jumped = oracle.run(one, n_traj=1, traj_id0=i, want_psi=True)
+    plain = oracle.run(dict(one, do_jumps=0), n_traj=1, traj_id0=i, want_psi=True)
+    assert jumped["n_jumps"][0] == 1
+    dr = 20.0 / 256
+    ru = np.arange(256) * dr * plain["psi"][0]
+    expect = ru / np.sqrt(dr * np.sum(np.abs(ru) ** 2))
+    assert np.max(np.abs(jumped["psi"][0] - expect)) < 1e-12
+
+
 def test_rmax_and_maxjumps(oracle_lib):
     cfg = W.base(N=128, L=20.0, dt=0.001, kappa_hat=20.0, n_traj=40, seed=5,
                  r_max=0.5, **W.constant_T(0.5, 300))
