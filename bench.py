@@ -11,16 +11,20 @@ qt_run, which is part of the timed region).
 value      FP32-bulk fused form (FP32 wave function and transforms, FP64 norm
            and threshold), whole-job trajectory-steps/s.
 extra      FP64 plain (unfused) and FP64 fused throughput on the same
-           workload, the FP32-bulk speedup over the plain FP64 form, FP32
-           against FP64 on one full run (near-threshold counts, jump
-           histories, largest differences away from the thresholds), the
-           uneven mixed-N batch, and p50/p99 request latency of a shortened
-           served stream.
+           workload (the same four runs, timed alike), the FP32-bulk speedup
+           over both, FP32 against FP64 on one full run (near-threshold
+           counts, jump histories, largest differences away from the
+           thresholds) and per observable against the number of steps, the
+           uneven mixed-N batch, the N=4096 checkpointed-segments batch, and
+           p50/p99 request latency of a shortened served stream.
 roofline   the fused kernel, algorithmic flops per trajectory-step
            F(N) = 10 N log2 N + 29 N (two complex DSTs at 5 N log2 N, three
            complex multiplies, norm and kernel arithmetic), divided by its
            average launch duration measured with HIP events on the stream it
-           runs on, against the FP32 vector peak.
+           runs on, against the FP32 vector peak; the same for the FP64 fused
+           kernel against the FP64 vector peak (roofline.fp64_fused), and the
+           plain FP64 form's algorithmic HBM bytes, 176 N per trajectory-step,
+           against 8 TB/s (roofline.fp64_plain).
 cpu_baseline  the FP64 oracle on the host cores on a bounded sample.
 """
 import argparse
@@ -35,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32 = 157.3e12       # MI355X FP32 vector, FLOP/s
 PEAK_FP64 = 78.6e12
+PEAK_HBM = 8.0e12
 
 
 def flops_per_traj_step(N):
@@ -74,8 +79,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the uneven-batch leg")
-    ap.add_argument("--c5", action="store_true",
-                    help="also run the N=4096 checkpointed-segments workload (about a minute)")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the N=4096 checkpointed-segments workload (about 50 s)")
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--profile", choices=["fp32", "fp64", "plain", "c5"], default=None,
                     help="profiling mode: one short run of the batch (--profile-steps time "
@@ -204,6 +209,38 @@ def precision_leg(ctx, qt, run, out64, n_traj, N, torch):
             "far_survival_max": float(np.abs(a["survival"][far] - b["survival"][far]).max()) if far.any() else None}
 
 
+def error_vs_steps_leg(ctx, qt, W, torch):
+    """FP32-bulk against FP64 fused (itself ~1e-12 from the oracle) on 512
+    trajectories of the N=2048 batch (kappa_hat=4, gamma_hat=0) cut at
+    several step counts: the largest error of each observable over the
+    trajectories whose norm never came within 1e-4 of a threshold, the wave
+    function split by whether the trajectory jumped."""
+    import numpy as np
+    rep = []
+    for steps in (100, 1000, 4000, 11899):
+        cfg = dict(W.c2_headline(4.0, 0.0, n_traj=512), max_steps=steps)
+        r = {}
+        for name, prec in (("a", qt.QT_FP64), ("b", qt.QT_FP32_BULK)):
+            r[name] = qt.to_numpy(qt.run(ctx, cfg, precision=prec, want_psi=True))
+        torch.cuda.synchronize()
+        a, b = r["a"], r["b"]
+        same = np.ones(512, bool)
+        for k in ("n_jumps", "l", "color", "status", "steps_done"):
+            same &= a[k] == b[k]
+        far = same & (np.minimum(a["min_gap"], b["min_gap"]) > 1e-4)
+        d = np.linalg.norm((a["psi"] - b["psi"]).reshape(512, -1), axis=1) / \
+            np.linalg.norm(a["psi"].reshape(512, -1), axis=1)
+        jumped = a["n_jumps"] > 0
+        mx = lambda v, m: float(v[m].max()) if m.any() else None
+        rep.append({"steps": steps, "far": int(far.sum()), "jump_histories_equal": int(same.sum()),
+                    "psi_no_jump": mx(d, far & ~jumped), "psi_jumped": mx(d, far & jumped),
+                    "norm_rel": mx(np.abs(a["norm"] - b["norm"]) / a["norm"], far),
+                    "overlap": mx(np.abs(a["overlap"] - b["overlap"]).max(axis=1), far),
+                    "survival": mx(np.abs(a["survival"] - b["survival"]).max(axis=1), far),
+                    "mean_r_rel": mx(np.abs(a["mean_r"] - b["mean_r"]) / a["mean_r"], far)})
+    return rep
+
+
 def segments_leg(ctx, qt, W, torch):
     """N=4096, 65,536 trajectories (three initial states), 20,000 steps as
     two captured segments of 10,000 steps, checkpointed every 1,000."""
@@ -278,25 +315,37 @@ def main():
     kernel_s = sum(kms) / 1e3 / len(kms)
     achieved = tps_per_run * flops_per_traj_step(N) / kernel_s
 
-    # FP64 fused and plain on one run each (kappa_hat=4, gamma_hat=0)
+    # FP64 fused and plain on the same runs, timed alike (one warmup each)
     extra = {}
-    wall64, k64 = timed_runs(qt.QT_FP64, qt.QT_FORM_FUSED, 1, out32, first=2)
-    extra["fp64_fused_traj_steps_per_s"] = tps_per_run / wall64
-    extra["fp64_fused_kernel_ms"] = k64[0]
+    timed_runs(qt.QT_FP64, qt.QT_FORM_FUSED, 1, out32)
+    wall64, k64 = timed_runs(qt.QT_FP64, qt.QT_FORM_FUSED, args.steps, out32, first=args.warmup)
+    extra["fp64_fused_traj_steps_per_s"] = tps_per_run * args.steps / wall64
+    extra["fp64_fused_kernel_ms"] = k64
+    k64_s = sum(k64) / 1e3 / len(k64)
+    achieved64 = tps_per_run * flops_per_traj_step(N) / k64_s
+    plain_roof = None
     if not args.no_plain:
-        wallp, kp = timed_runs(qt.QT_FP64, qt.QT_FORM_PLAIN, 1, out32, first=2)
-        extra["fp64_plain_traj_steps_per_s"] = tps_per_run / wallp
-        extra["fp64_plain_kernel_ms"] = kp[0]
+        timed_runs(qt.QT_FP64, qt.QT_FORM_PLAIN, 1, out32)
+        wallp, kp = timed_runs(qt.QT_FP64, qt.QT_FORM_PLAIN, args.steps, out32, first=args.warmup)
+        extra["fp64_plain_traj_steps_per_s"] = tps_per_run * args.steps / wallp
+        extra["fp64_plain_kernel_ms"] = kp
         extra["speedup_fp32_bulk_over_fp64_plain"] = value / extra["fp64_plain_traj_steps_per_s"]
+        kp_s = sum(kp) / 1e3 / len(kp)
+        bw = tps_per_run * 176.0 * N / kp_s
+        plain_roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                      "frac": bw / PEAK_HBM, "kernel_ms": kp_s * 1e3,
+                      "bytes_per_traj_step": 176 * N}
     extra["speedup_fp32_bulk_over_fp64_fused"] = value / extra["fp64_fused_traj_steps_per_s"]
     extra["plan"] = {"fp32_threads_per_traj": w32, "fp32_traj_per_cu": s32,
                      "fp64_threads_per_traj": w64, "fp64_traj_per_cu": s64}
+    qt.run(ctx, runs[2], precision=qt.QT_FP64, out=out32)      # the FP64 results of run 2
     extra["fp32_vs_fp64"] = precision_leg(ctx, qt, runs[2], out32, n_traj, N, torch)
+    extra["fp32_error_vs_steps"] = error_vs_steps_leg(ctx, qt, W, torch)
 
     extra["c2_no_jump_shortcut"] = shortcut_leg(ctx, qt, runs, out32, torch)
     if not args.no_c3:
         extra["c3_uneven"] = uneven_leg(ctx, qt, W, torch)
-    if args.c5:
+    if not args.no_c5:
         extra["c5_segments"] = segments_leg(ctx, qt, W, torch)
 
     if not args.no_serve:
@@ -357,7 +406,12 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
                      "traffic": measured_traffic("fused_kernel<float, 2048"),
                      "kernel_ms": kernel_s * 1e3,
-                     "flops_per_traj_step": flops_per_traj_step(N)},
+                     "flops_per_traj_step": flops_per_traj_step(N),
+                     "fp64_fused": {"bound": "alu", "achieved": achieved64 / 1e12,
+                                    "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                                    "frac": achieved64 / PEAK_FP64, "kernel_ms": k64_s * 1e3,
+                                    "traffic": measured_traffic("fused_kernel<double, 2048")},
+                     "fp64_plain": plain_roof},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -20,9 +20,10 @@ from paper_2107_06147_amd import workloads as W
 
 
 def replay(ctx, requests, precision=qt.QT_FP32_BULK, segment_steps=500, rate_scale=1.0,
-           steps_cap=None, hbm_budget_bytes=0):
+           steps_cap=None, hbm_budget_bytes=0, progress_s=None):
     """Submits `requests` [(arrival_s, cfg)] at their (scaled) arrival times,
-    waits for all, returns per-request latencies and the server's stats."""
+    waits for all, returns per-request latencies and the server's stats.
+    progress_s: print a progress line every that many seconds."""
     srv = qt.Server(ctx, precision=precision, segment_steps=segment_steps,
                     hbm_budget_bytes=hbm_budget_bytes)
     ids = []
@@ -31,14 +32,24 @@ def replay(ctx, requests, precision=qt.QT_FP32_BULK, segment_steps=500, rate_sca
     lock = threading.Lock()
     submitted = threading.Event()
 
+    last_print = [time.perf_counter()]
+
     def watch():
         # completion times, taken while requests are still being submitted
         while True:
             with lock:
                 open_ids = [r for r in ids if r not in t_done]
                 finished_submitting = submitted.is_set()
+                n_sub, n_done = len(ids), len(t_done)
             if finished_submitting and not open_ids:
                 return
+            now = time.perf_counter()
+            if progress_s and now - last_print[0] >= progress_s:
+                last_print[0] = now
+                st = srv.stats()
+                print("serve: %.0f s, %d submitted, %d done, %d running, %d queued, %.3g traj-steps/s busy"
+                      % (now - start, n_sub, n_done, st["running"], st["queued"],
+                         st["traj_steps_per_s"]), flush=True)
             for r in open_ids:
                 if srv.poll(r):
                     now = time.perf_counter()
@@ -46,9 +57,9 @@ def replay(ctx, requests, precision=qt.QT_FP32_BULK, segment_steps=500, rate_sca
                         t_done[r] = now
             time.sleep(0.001)
 
+    start = time.perf_counter()
     watcher = threading.Thread(target=watch, daemon=True)
     watcher.start()
-    start = time.perf_counter()
     offered = 0
     for (t_arr, cfg) in requests:
         if steps_cap is not None:
@@ -70,7 +81,10 @@ def replay(ctx, requests, precision=qt.QT_FP32_BULK, segment_steps=500, rate_sca
     stats = srv.stats()
     srv.close()
     v = np.array(sorted(lat.values()))
+    order = sorted(ids, key=lambda r: t_submit[r])
     return {
+        "latency_by_arrival_decile_s": [float(np.median([lat[r] for r in part]))
+                                        for part in np.array_split(np.array(order), 10) if len(part)],
         "requests": len(ids),
         "trajectories": offered,
         "p50_latency_s": float(np.percentile(v, 50)) if len(v) else None,
@@ -102,3 +116,30 @@ def bench_stream(ctx, duration_s=6.0, rate_scale=1.0, steps_cap=None, segment_st
     rep.update({"arrival_rate_per_s": 20.0 / rate_scale, "duration_s": duration_s,
                 "steps_cap": steps_cap, "segment_steps": segment_steps})
     return rep
+
+
+if __name__ == "__main__":
+    # the served stream over its whole duration: python -m
+    # paper_2107_06147_amd.serve [--duration 120] [--rate-scale 1]
+    import argparse
+    import json
+
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--duration", type=float, default=120.0)
+    ap.add_argument("--rate-scale", type=float, default=1.0)
+    ap.add_argument("--segment-steps", type=int, default=500)
+    a = ap.parse_args()
+    torch.cuda.set_device(0)
+    c = qt.Context(0)
+    for n in (1024, 2048):
+        c.plan(n, qt.QT_FP32_BULK, tune=True)
+    reqs = W.c4_requests(duration_s=a.duration)
+    off = offered_load(duration_s=a.duration) / a.rate_scale
+    print("serve: %d requests over %.0f s, offered %.3g traj-steps/s" % (len(reqs), a.duration * a.rate_scale, off),
+          flush=True)
+    rep, _ = replay(c, reqs, rate_scale=a.rate_scale, segment_steps=a.segment_steps, progress_s=10.0)
+    rep.update({"arrival_rate_per_s": 20.0 / a.rate_scale, "duration_s": a.duration,
+                "offered_load_traj_steps_per_s": off, "segment_steps": a.segment_steps})
+    print(json.dumps(rep))
+    c.close()
