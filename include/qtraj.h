@@ -234,8 +234,13 @@ qt_status qt_job_results(qt_job* job, const qt_results* dev_out, void* hip_strea
 qt_status qt_job_destroy(qt_job* job);
 
 /* Continuous-batching server.  Requests (a batch each) are admitted while
- * others run, as device memory within hbm_budget_bytes and persistent slots
- * free up; admission happens at segment boundaries of segment_steps steps.
+ * others run, in arrival order, as device memory within hbm_budget_bytes and
+ * persistent slots free up: a request is admitted while the admitted
+ * trajectories, counted against the device's resident slots of their grid
+ * size (compute units times workgroups per CU of the kernel variant), stay
+ * within max_occupancy; when nothing runs, the next request is admitted
+ * whatever its size.  Admission happens at segment boundaries of
+ * segment_steps steps.
  * qt_submit copies its inputs and returns at once; qt_wait copies a finished
  * request's results to HOST pointers.  A request that could not run (its
  * device memory could not be allocated at admission, a launch or the copy
@@ -246,6 +251,13 @@ typedef struct {
     size_t  hbm_budget_bytes;     /* 0: 50% of free device memory             */
     int64_t segment_steps;        /* steps per admission round (e.g. 500)     */
     int32_t precision;            /* qt_precision of every request            */
+    int32_t pad0;
+    double  max_occupancy;        /* admitted trajectories per resident slot; 0:
+                                     8 (< 0: no slot limit, memory only).  A
+                                     round runs every admitted trajectory
+                                     segment_steps steps, a whole number of
+                                     them per slot: at k per slot the device
+                                     is about k / ceil(k) busy            */
 } qt_server_cfg;
 
 typedef struct {

@@ -870,6 +870,8 @@ qt_status qt_context_destroy(qt_context* ctx)
     for (auto& kv : ctx->phase) hipFree(kv.second);
     for (auto& kv : ctx->ksu_phi) hipFree(kv.second);
     for (hipStream_t s : ctx->aux) hipStreamDestroy(s);
+    for (hipEvent_t e : ctx->join) hipEventDestroy(e);
+    if (ctx->fork) hipEventDestroy(ctx->fork);
     hipEventDestroy(ctx->ev0);
     hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -967,10 +969,24 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
         QT_HIP(hipMemcpyAsync(d_ii, ii2.data(), n_items * 8, hipMemcpyHostToDevice, s));
         QT_HIP(hipStreamSynchronize(s));
     }
-    QT_HIP(hipEventRecord(ctx->ev0, s));
-    int64_t launches = 0;
-    for (size_t c = 0; c < Ns.size(); ++c) {
-        if (count[c] == 0) continue;
+    // The classes run concurrently, each on a stream of its own (the
+    // caller's for the first, the context's fork streams, all of default
+    // priority, for the others): the workgroups of a class take the CUs that
+    // the tail of another class frees instead of waiting for its whole
+    // launch to end.  Classes start in the order of their longest item (the
+    // items of a class are in LPT order, its first is its longest).
+    std::vector<size_t> order;
+    for (size_t c = 0; c < Ns.size(); ++c)
+        if (count[c] > 0) order.push_back(c);
+    auto item_cost = [&](size_t k) {
+        const HostBatch& h = *hb[ig2[k]];
+        return (double)h.n_steps * h.phys.N * std::log2((double)h.phys.N);
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return item_cost(start[x]) > item_cost(start[y]); });
+    std::vector<ClassLaunch> cl;
+    for (size_t k = 0; k < order.size(); ++k) {
+        const size_t c = order[k];
         const int N = Ns[c] / 2, pot = Ns[c] % 2;
         int W = 0, slots = 0;
         fused_launcher launch = nullptr;
@@ -987,15 +1003,45 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
         a.prew = t.prew;
         a.seg_steps = 0;
         const int grid = (int)std::min<int64_t>((int64_t)count[c], (int64_t)ctx->n_cu * slots);
-        QT_HIP(launch_queue_reset(a.queue, s));
-        QT_HIP(launch(a, grid, s));
-        launches += 2;
+        cl.push_back(ClassLaunch{launch, a, grid});
     }
+    QT_HIP(hipEventRecord(ctx->ev0, s));
+    if ((st = launch_classes(cl, s, &ctx->fork, &ctx->aux, &ctx->join)) != QT_OK) return st;
+    const int64_t launches = 2 * (int64_t)cl.size();
     QT_HIP(hipEventRecord(ctx->ev1, s));
     ctx->timed = true;
     ctx->last_launches = launches;
     QT_HIP(hipFreeAsync(mem, s));
     QT_HIP(hipFreeAsync(dg.mem, s));
+    return QT_OK;
+}
+
+qt_status launch_classes(const std::vector<ClassLaunch>& v, hipStream_t s, hipEvent_t* fork,
+                         std::vector<hipStream_t>* streams, std::vector<hipEvent_t>* joins)
+{
+    if (v.empty()) return QT_OK;
+    if (v.size() > 1) {
+        if (!*fork) QT_HIP(hipEventCreateWithFlags(fork, hipEventDisableTiming));
+        while (streams->size() + 1 < v.size()) {
+            hipStream_t a = nullptr;
+            hipEvent_t e = nullptr;
+            QT_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+            streams->push_back(a);
+            QT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            joins->push_back(e);
+        }
+        QT_HIP(hipEventRecord(*fork, s));
+    }
+    for (size_t k = 0; k < v.size(); ++k) {
+        hipStream_t cs = k == 0 ? s : (*streams)[k - 1];
+        if (k > 0) QT_HIP(hipStreamWaitEvent(cs, *fork, 0));
+        QT_HIP(launch_queue_reset(v[k].args.queue, cs));
+        QT_HIP(v[k].launch(v[k].args, v[k].grid, cs));
+    }
+    for (size_t k = 1; k < v.size(); ++k) {
+        QT_HIP(hipEventRecord((*joins)[k - 1], (*streams)[k - 1]));
+        QT_HIP(hipStreamWaitEvent(s, (*joins)[k - 1], 0));
+    }
     return QT_OK;
 }
 

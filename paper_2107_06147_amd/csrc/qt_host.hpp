@@ -23,6 +23,8 @@ struct qt_context {
     bool timed = false;
     int64_t last_launches = 0;
     std::vector<hipStream_t> aux;                          // fork/join streams
+    std::vector<hipEvent_t> join;                          // their join events
+    hipEvent_t fork = nullptr;                             // the fork point
     // static phase tables exp(-i dt/2 V_static) per (l, colour), keyed by
     // (precision, N, L, mass, alpha_s, dt)
     std::map<std::vector<double>, void*> phase;
@@ -146,6 +148,20 @@ qt_status run_vacuum_phases(qt_context* ctx, const std::vector<HostBatch*>& hb, 
 qt_status add_zeroth_groups(const std::vector<HostBatch*>& hb, std::vector<HostBatch>* zb,
                             std::vector<const HostBatch*>* v, std::vector<qt_results>* outs,
                             hipStream_t s, void** mem);
+
+// One persistent launch of the fused kernel (one class of items).
+struct ClassLaunch {
+    fused_launcher launch = nullptr;
+    FusedArgs args{};
+    int grid = 0;
+};
+// Launches the classes concurrently: the first on `s`, the others on fork
+// streams of default priority (created into `streams`/`joins` as needed,
+// owned by the caller, which must not use them from two threads at once),
+// each after `fork` recorded on `s` and joined back into `s`.  Each launch
+// is preceded by its queue reset on its own stream.
+qt_status launch_classes(const std::vector<ClassLaunch>& v, hipStream_t s, hipEvent_t* fork,
+                         std::vector<hipStream_t>* streams, std::vector<hipEvent_t>* joins);
 
 // LPT order of (group, index) items: longest remaining work first.
 void build_items(const std::vector<const HostBatch*>& hb, std::vector<int32_t>* ig,

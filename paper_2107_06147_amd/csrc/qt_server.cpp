@@ -1,11 +1,15 @@
 // qt_server.cpp -- continuous-batching request server.
 //
 // Requests (one batch each) are queued by qt_submit.  A scheduler thread runs
-// rounds: at each round boundary it admits queued requests while their
-// device memory fits the HBM budget, then runs every unfinished trajectory of
+// rounds: at each round boundary it admits queued requests, in arrival
+// order, while their device memory fits the HBM budget and their
+// trajectories fit the device's resident slots (times max_occupancy: slots
+// kept busy, the queue taking the excess instead of every running request
+// slowing down), then runs every unfinished trajectory of
 // every admitted request for up to segment_steps steps, in one persistent
 // launch per grid size N (trajectories of different requests share the
-// launch and refill the same workgroups), and retires finished requests:
+// launch and refill the same workgroups; the launches of the grid sizes
+// run concurrently), and retires finished requests:
 // their results are copied to host memory, their device memory is freed and
 // their latency (completion - submission) is recorded.  A trajectory's
 // result depends only on its own inputs and ids and on the kernel variant,
@@ -16,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -46,6 +51,7 @@ struct Request {
     TrajState* st = nullptr;
     void* st_psi = nullptr;
     size_t bytes = 0;
+    double occ = 0.0;             // its trajectories per resident slot
     // host results once done
     std::vector<double> norm, first_r, overlap, survival, mean_r, min_gap;
     std::vector<int32_t> l, color, n_jumps, status;
@@ -68,6 +74,7 @@ struct qt_server {
     qt_context* ctx = nullptr;
     qt_server_cfg cfg{};
     size_t budget = 0, in_use = 0;
+    double max_occ = 8.0, occ = 0.0;   // admitted trajectories per resident slot
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Request>> queue;
@@ -84,6 +91,10 @@ struct qt_server {
     double busy_s = 0.0;
     std::string error;
     std::map<int, Variant> variants;   // by 2 N + potential
+    // fork streams of the concurrent per-N launches of a round
+    std::vector<hipStream_t> fork_streams;
+    std::vector<hipEvent_t> fork_joins;
+    hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -132,6 +143,19 @@ void release(Request& q)
     hipFree(q.dg.mem);
     q.res.mem = q.st = nullptr;
     q.st_psi = q.dg.mem = nullptr;
+}
+
+// The kernel variant of (N, potential), fixed at its first use.
+qt_status server_variant(qt_server* s, int N, int pot, Variant** out)
+{
+    Variant& v = s->variants[2 * N + pot];
+    if (!v.launch) {
+        std::lock_guard<std::mutex> lk(s->ctx->mu);
+        qt_status st = pick_launcher(s->ctx, s->cfg.precision, N, pot, &v.W, &v.launch, &v.slots);
+        if (st != QT_OK) return st;
+    }
+    *out = &v;
+    return QT_OK;
 }
 
 // Marks q failed with the calling thread's last error (the caller holds s->mu).
@@ -215,21 +239,20 @@ qt_status run_round(qt_server* s, int64_t* advanced)
         QT_HIP(hipMemcpyAsync(ig, hig.data(), n_items * 4, hipMemcpyHostToDevice, s->stream));
         QT_HIP(hipMemcpyAsync(ii, hii.data(), n_items * 8, hipMemcpyHostToDevice, s->stream));
     }
+    std::vector<ClassLaunch> cl;
     for (size_t c = 0; c < Ns.size(); ++c) {
         if (!count[c]) continue;
         const int N = Ns[c] / 2, pot = Ns[c] % 2;
         qt_context::Tables t;
         qt_status st;
-        Variant& v = s->variants[Ns[c]];
+        Variant* v = nullptr;
+        if ((st = server_variant(s, N, pot, &v)) != QT_OK) return st;
         {
             std::lock_guard<std::mutex> lk(s->ctx->mu);
-            if (!v.launch &&
-                (st = pick_launcher(s->ctx, prec, N, pot, &v.W, &v.launch, &v.slots)) != QT_OK)
-                return st;
             if ((st = ensure_tables(s->ctx, prec, N, &t)) != QT_OK) return st;
         }
-        const fused_launcher launch = v.launch;
-        const int slots = v.slots;
+        const fused_launcher launch = v->launch;
+        const int slots = v->slots;
         FusedArgs a;
         a.groups = dgroups;
         a.item_group = ig + start[c];
@@ -240,9 +263,12 @@ qt_status run_round(qt_server* s, int64_t* advanced)
         a.prew = t.prew;
         a.seg_steps = s->cfg.segment_steps;
         const int grid = (int)std::min<int64_t>((int64_t)count[c], (int64_t)s->ctx->n_cu * slots);
-        QT_HIP(launch_queue_reset(a.queue, s->stream));
-        QT_HIP(launch(a, grid, s->stream));
+        cl.push_back(ClassLaunch{launch, a, grid});
     }
+    // the N classes of the round run concurrently (see launch_classes)
+    if (qt_status st = launch_classes(cl, s->stream, &s->fork, &s->fork_streams, &s->fork_joins);
+        st != QT_OK)
+        return st;
     QT_HIP(hipStreamSynchronize(s->stream));
     // progress: read the state records back
     for (auto& q : s->running) {
@@ -274,13 +300,14 @@ void server_loop(qt_server* s)
                 if ((*it)->cancel) {
                     release(**it);
                     s->in_use -= (*it)->bytes;
+                    s->occ -= (*it)->occ;
                     (*it)->state = CANCELED;
                     it = s->running.erase(it);
                 } else {
                     ++it;
                 }
             }
-            // admission by HBM budget
+            // admission in arrival order, by HBM budget and resident slots
             while (!s->queue.empty()) {
                 auto q = s->queue.front();
                 if (q->cancel) {
@@ -289,9 +316,21 @@ void server_loop(qt_server* s)
                     continue;
                 }
                 const size_t b = request_bytes(q->hb, s->cfg.precision);
-                if (!s->running.empty() && s->in_use + b > s->budget) break;
+                Variant* v = nullptr;
+                const qt_status vst = server_variant(s, q->hb.phys.N, q->hb.phys.potential, &v);
+                if (vst != QT_OK) {
+                    s->queue.pop_front();
+                    mark_failed(*q, vst);
+                    continue;
+                }
+                const double o = (double)q->hb.batch.n_traj /
+                                 ((double)s->ctx->n_cu * std::max(v->slots, 1));
+                if (!s->running.empty() &&
+                    (s->in_use + b > s->budget || (s->max_occ > 0 && s->occ + o > s->max_occ)))
+                    break;
                 s->queue.pop_front();
                 q->bytes = b;
+                q->occ = o;
                 const qt_status ast = admit(s, *q);
                 if (ast != QT_OK) {
                     // this request fails with the cause; the others go on
@@ -300,6 +339,7 @@ void server_loop(qt_server* s)
                     continue;
                 }
                 s->in_use += b;
+                s->occ += o;
                 s->admitted++;
                 s->running.push_back(q);
             }
@@ -321,6 +361,7 @@ void server_loop(qt_server* s)
             }
             s->running.clear();
             s->in_use = 0;
+            s->occ = 0.0;
             s->cv_done.notify_all();
             continue;
         }
@@ -342,6 +383,7 @@ void server_loop(qt_server* s)
                 if (fst != QT_OK) mark_failed(*q, fst);
                 release(*q);
                 s->in_use -= q->bytes;
+                s->occ -= q->occ;
                 q->t_done = Clock::now();
                 s->latencies.push_back(std::chrono::duration<double>(q->t_done - q->t_submit).count());
                 s->completed++;
@@ -366,6 +408,7 @@ qt_status qt_server_create(qt_context* ctx, const qt_server_cfg* cfg, qt_server*
     if (!ctx || !cfg || !out) return fail(QT_EINVAL, "null argument");
     if (cfg->segment_steps < 1) return fail(QT_EINVAL, "segment_steps must be >= 1");
     if (cfg->precision != QT_FP64 && cfg->precision != QT_FP32_BULK) return fail(QT_EINVAL, "bad precision");
+    if (!std::isfinite(cfg->max_occupancy)) return fail(QT_EINVAL, "max_occupancy must be finite");
     QT_HIP(hipSetDevice(ctx->device));
     auto* s = new qt_server();
     s->ctx = ctx;
@@ -376,6 +419,7 @@ qt_status qt_server_create(qt_context* ctx, const qt_server_cfg* cfg, qt_server*
         return fail(QT_EDEVICE, "hipMemGetInfo failed");
     }
     s->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : fr / 2;
+    s->max_occ = cfg->max_occupancy == 0.0 ? 8.0 : cfg->max_occupancy;
     if (hipStreamCreate(&s->stream) != hipSuccess) {
         delete s;
         return fail(QT_EDEVICE, "hipStreamCreate failed");
@@ -524,6 +568,9 @@ qt_status qt_server_destroy(qt_server* s)
     hipSetDevice(s->ctx->device);
     for (auto& q : s->running) release(*q);
     if (s->misc) hipFree(s->misc);
+    for (hipStream_t a : s->fork_streams) hipStreamDestroy(a);
+    for (hipEvent_t e : s->fork_joins) hipEventDestroy(e);
+    if (s->fork) hipEventDestroy(s->fork);
     if (s->stream) hipStreamDestroy(s->stream);
     delete s;
     return QT_OK;

@@ -68,7 +68,7 @@ class qt_results(C.Structure):
 
 class qt_server_cfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("segment_steps", C.c_int64),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("pad0", C.c_int32), ("max_occupancy", C.c_double)]
 
 
 class qt_stats(C.Structure):
@@ -499,8 +499,10 @@ class Job:
 class Server:
     """Continuous-batching server (qt_server_*)."""
 
-    def __init__(self, ctx, precision=QT_FP32_BULK, segment_steps=500, hbm_budget_bytes=0):
-        cfg = qt_server_cfg(int(hbm_budget_bytes), int(segment_steps), int(precision))
+    def __init__(self, ctx, precision=QT_FP32_BULK, segment_steps=500, hbm_budget_bytes=0,
+                 max_occupancy=0.0):
+        cfg = qt_server_cfg(int(hbm_budget_bytes), int(segment_steps), int(precision), 0,
+                            float(max_occupancy))
         h = _VP()
         check(lib().qt_server_create(ctx.h, C.byref(cfg), C.byref(h)), "qt_server_create")
         self.h = h

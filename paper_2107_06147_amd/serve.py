@@ -20,12 +20,12 @@ from paper_2107_06147_amd import workloads as W
 
 
 def replay(ctx, requests, precision=qt.QT_FP32_BULK, segment_steps=500, rate_scale=1.0,
-           steps_cap=None, hbm_budget_bytes=0, progress_s=None):
+           steps_cap=None, hbm_budget_bytes=0, progress_s=None, max_occupancy=0.0):
     """Submits `requests` [(arrival_s, cfg)] at their (scaled) arrival times,
     waits for all, returns per-request latencies and the server's stats.
     progress_s: print a progress line every that many seconds."""
     srv = qt.Server(ctx, precision=precision, segment_steps=segment_steps,
-                    hbm_budget_bytes=hbm_budget_bytes)
+                    hbm_budget_bytes=hbm_budget_bytes, max_occupancy=max_occupancy)
     ids = []
     t_submit = {}
     t_done = {}
@@ -129,6 +129,8 @@ if __name__ == "__main__":
     ap.add_argument("--duration", type=float, default=120.0)
     ap.add_argument("--rate-scale", type=float, default=1.0)
     ap.add_argument("--segment-steps", type=int, default=500)
+    ap.add_argument("--max-occupancy", type=float, default=0.0,
+                    help="admitted trajectories per resident slot (0: the server's default)")
     a = ap.parse_args()
     torch.cuda.set_device(0)
     c = qt.Context(0)
@@ -138,8 +140,10 @@ if __name__ == "__main__":
     off = offered_load(duration_s=a.duration) / a.rate_scale
     print("serve: %d requests over %.0f s, offered %.3g traj-steps/s" % (len(reqs), a.duration * a.rate_scale, off),
           flush=True)
-    rep, _ = replay(c, reqs, rate_scale=a.rate_scale, segment_steps=a.segment_steps, progress_s=10.0)
+    rep, _ = replay(c, reqs, rate_scale=a.rate_scale, segment_steps=a.segment_steps, progress_s=10.0,
+                    max_occupancy=a.max_occupancy)
     rep.update({"arrival_rate_per_s": 20.0 / a.rate_scale, "duration_s": a.duration,
-                "offered_load_traj_steps_per_s": off, "segment_steps": a.segment_steps})
+                "offered_load_traj_steps_per_s": off, "segment_steps": a.segment_steps,
+                "max_occupancy": a.max_occupancy})
     print(json.dumps(rep))
     c.close()
