@@ -46,13 +46,17 @@ def flops_per_traj_step(N):
     return 10.0 * N * math.log2(N) + 29.0 * N
 
 
+# the sources of the fused kernels (device code and what it includes)
+KERNEL_SOURCES = ("qt_fused.hpp", "qt_device.hpp", "qt_dst32.hpp", "qt_philox.h", "qt_internal.h",
+                  "qt_kernels.hip", "qt_kernels_ksu.hip")
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2107_06147_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -29,6 +30,31 @@ constexpr double kPi = 3.14159265358979323846;
 
 namespace qt {
 thread_local bool g_no_alloc = false;
+
+bool trace_on()
+{
+    const char* e = std::getenv("QTRAJ_TRACE");
+    return e && *e;
+}
+
+void trace_line(const char* fmt, ...)
+{
+    static std::mutex mu;
+    const char* e = std::getenv("QTRAJ_TRACE");
+    if (!e || !*e) return;
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::lock_guard<std::mutex> lk(mu);
+    const bool err = std::strcmp(e, "stderr") == 0 || std::strcmp(e, "-") == 0;
+    FILE* f = err ? stderr : std::fopen(e, "a");
+    if (!f) return;
+    std::fprintf(f, "%s\n", buf);
+    if (err) std::fflush(f);
+    else std::fclose(f);
+}
 }  // namespace qt
 
 namespace qt {
@@ -1009,6 +1035,17 @@ qt_status run_fused_groups(qt_context* ctx, const std::vector<const HostBatch*>&
     if ((st = launch_classes(cl, s, &ctx->fork, &ctx->aux, &ctx->join)) != QT_OK) return st;
     const int64_t launches = 2 * (int64_t)cl.size();
     QT_HIP(hipEventRecord(ctx->ev1, s));
+    if (trace_on()) {
+        QT_HIP(hipEventSynchronize(ctx->ev1));
+        float ms = 0.f;
+        QT_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        std::string ns;
+        for (size_t k = 0; k < order.size(); ++k)
+            ns += (k ? "," : "") + std::to_string(Ns[order[k]] / 2);
+        trace_line("{\"event\": \"run\", \"precision\": %d, \"batches\": %zu, \"items\": %zu, "
+                   "\"N_classes\": [%s], \"kernel_ms\": %.3f}",
+                   prec, hb.size(), n_items, ns.c_str(), ms);
+    }
     ctx->timed = true;
     ctx->last_launches = launches;
     QT_HIP(hipFreeAsync(mem, s));

@@ -48,6 +48,12 @@ namespace qt {
 
 qt_status fail(qt_status s, const char* fmt, ...);
 
+// QTRAJ_TRACE (environment): when it names a file (or "stderr"), runs, job
+// segments and server rounds each append one JSON line there, after their
+// device work has finished (tracing synchronises the stream it traces).
+bool trace_on();
+void trace_line(const char* fmt, ...);
+
 // Set while the calling thread runs qt_run_noalloc: a context table, basis or
 // plan that would have to be built (device allocation) is an error instead.
 extern thread_local bool g_no_alloc;

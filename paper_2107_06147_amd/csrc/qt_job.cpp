@@ -211,6 +211,14 @@ qt_status qt_job_advance(qt_job* j, int64_t steps, void* hip_stream)
     QT_HIP(hipStreamWaitEvent(us, j->ev_out, 0));
     j->ctx->timed = true;
     j->ctx->last_launches = 2 * launches;
+    if (trace_on()) {
+        QT_HIP(hipEventSynchronize(j->ctx->ev1));
+        float ms = 0.f;
+        QT_HIP(hipEventElapsedTime(&ms, j->ctx->ev0, j->ctx->ev1));
+        trace_line("{\"event\": \"segment\", \"N\": %d, \"precision\": %d, \"trajectories\": %lld, "
+                   "\"steps\": %lld, \"launches\": %lld, \"kernel_ms\": %.3f}",
+                   j->N, j->prec, (long long)j->n_traj, (long long)steps, (long long)launches, ms);
+    }
     return QT_OK;
 }
 

@@ -395,6 +395,10 @@ void server_loop(qt_server* s)
         }
         (void)adv;
         s->traj_steps += delta;
+        if (trace_on())
+            trace_line("{\"event\": \"round\", \"running\": %zu, \"queued\": %zu, "
+                       "\"occupancy\": %.3f, \"traj_steps\": %lld, \"wall_ms\": %.3f}",
+                       s->running.size(), s->queue.size(), s->occ, (long long)delta, dt * 1e3);
         s->cv_done.notify_all();
     }
 }

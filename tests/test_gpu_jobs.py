@@ -293,3 +293,28 @@ def test_c5_full_batch_sampled(ctx):
             one = {key: v[k:k + 1] for key, v in out.items()}
             compare(ref, one, F32, check_psi=False, label="c5 id %d" % tid)
 
+
+
+def test_trace_lines(ctx, tmp_path, monkeypatch):
+    """QTRAJ_TRACE names a file: a run, a job segment and a server round each
+    append one JSON line with their sizes and device time."""
+    import json
+    path = tmp_path / "trace.jsonl"
+    monkeypatch.setenv("QTRAJ_TRACE", str(path))
+    cfg = _cfg(512, 60)
+    gpu_run(ctx, cfg, F32)
+    job = qt.Job(ctx, cfg, precision=F32, segment_steps=25)
+    job.advance(50)
+    job.done()
+    job.close()
+    srv = qt.Server(ctx, precision=F32, segment_steps=100)
+    srv.wait(srv.submit(_requests()[0]), timeout_s=120)
+    srv.close()
+    monkeypatch.delenv("QTRAJ_TRACE")
+    lines = [json.loads(x) for x in open(path)]
+    ev = {x["event"]: x for x in lines}
+    assert {"run", "segment", "round"} <= set(ev)
+    assert ev["run"]["items"] == cfg["n_traj"] and ev["run"]["N_classes"] == [512]
+    assert ev["run"]["kernel_ms"] > 0
+    assert ev["segment"]["steps"] == 50 and ev["segment"]["launches"] == 2
+    assert ev["round"]["traj_steps"] > 0

@@ -320,3 +320,37 @@ def test_ksu_rejects_jumps_and_octet(ctx):
     with pytest.raises(qt.QtError):
         gpu_run(ctx, dict(cfg, do_jumps=0, init_color=W.OCTET, init_kind=W.INIT_GAUSSIAN,
                           init_width=1.0), F64)
+
+
+# ------------------------------- the N = 2048 batch over its whole length
+
+def _c2_goldens():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_full_length_oracle.json")
+    return json.load(open(path))["rows"]
+
+
+@pytest.mark.parametrize("form", [FUSED, PLAIN])
+def test_fp64_full_length_against_oracle_goldens(ctx, form):
+    """FP64 over all 11,899 steps of the N = 2048 Bjorken batch, two
+    trajectories of each (kappa_hat, gamma_hat) run, against the oracle's
+    results stored by tests/golden/make_c2_full_length.py: every result and
+    the whole jump sequence, to the FP64 bar (1e-10)."""
+    rows = _c2_goldens()
+    for run in sorted({(r["kappa_hat"], r["gamma_hat"]) for r in rows}):
+        cfg = W.c2_headline(*run)
+        for r in [x for x in rows if (x["kappa_hat"], x["gamma_hat"]) == run]:
+            out = gpu_run(ctx, cfg, F64, form, want_psi=False, n_traj=1, traj_id0=r["traj_id"],
+                          jump_log_cap=64)
+            assert r["min_gap"] > FP64_DELTA                 # decisions well away from 1e-9
+            for key in ("status", "steps_done", "n_jumps", "l", "color"):
+                assert out[key][0] == r[key], (run, r["traj_id"], key)
+            assert out["steps_done"][0] == r["n_steps"] == 11899
+            np.testing.assert_array_equal(out["jump_log"][0, :len(r["jump_log"])],
+                                          np.array(r["jump_log"], dtype=np.int32).reshape(-1, 3))
+            assert out["first_r"][0] == r["first_r"]
+            assert abs(out["norm"][0] - r["norm"]) <= 1e-10
+            assert np.max(np.abs(out["overlap"][0] - r["overlap"])) <= 1e-10
+            assert np.max(np.abs(out["survival"][0] - r["survival"])) <= 1e-10
+            assert abs(out["mean_r"][0] - r["mean_r"]) <= 1e-9 * r["mean_r"]
