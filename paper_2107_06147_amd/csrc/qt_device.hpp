@@ -389,6 +389,23 @@ __device__ __forceinline__ void fft_passes_held(cx<R>* v, const Lanes<N, W>& ln,
     }
 }
 
+// fft_passes_held with two exchange buffers as there, but each pass's
+// twiddles loaded before the exchange that precedes it instead of held for
+// the whole FFT (fewer registers; their latency overlaps the exchange).
+template <class R, int N, int W, int p>
+__device__ __forceinline__ void fft_passes_db(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf,
+                                              cx<R>* buf2, const cx<R>* __restrict__ tw,
+                                              const PassTwiddles<R, N, W, p>& cur)
+{
+    fft_pass<R, N, W, p>(v, cur);
+    if constexpr (p + 1 < Plan<N, W>::NPASS) {
+        PassTwiddles<R, N, W, p + 1> nxt;
+        nxt.load(ln, opaque(tw));
+        fft_exchange<R, N, W, p>(v, ln, buf);
+        fft_passes_db<R, N, W, p + 1>(v, ln, buf2, buf, tw, nxt);
+    }
+}
+
 // ------------------------------------------------------- reductions -------
 
 // Cross-lane moves with the data-parallel-primitives (DPP) modifier: a VALU
@@ -530,8 +547,10 @@ __device__ __forceinline__ void load_prew(cx<R>* pw, const cx<R>* prew, const La
 // On entry a/b hold x in the mirror layout and pw the weights (load_prew);
 // prew is the weight table (lane 0 reads its second column from it).  On
 // exit a/b hold F (times the kinetic factor of each output if KIN) in the
-// same layout.
-template <class R, int N, int W, bool KIN>
+// same layout.  The kinetic factors are loaded before the prefix sum, whose
+// exchanges hide their latency, or, LATE_KIN, where they are used (fewer
+// registers held across the sum).
+template <class R, int N, int W, bool KIN, bool LATE_KIN = false>
 __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const cx<R>* prew,
                                      const Lanes<N, W>& ln_in, cx<R>* buf, cx<R>* wsum,
                                      const cx<R>* __restrict__ tw,
@@ -617,8 +636,9 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const 
     }
     // kinetic factors of the outputs this lane ends up holding (mirror
     // layout), loaded here so that the exchanges below hide their latency
-    Kin<R> kk[KIN ? PL::P : 1];
-    if constexpr (KIN) {
+    constexpr bool kEarly = KIN && !LATE_KIN;
+    Kin<R> kk[kEarly ? PL::P : 1];
+    if constexpr (kEarly) {
         kin = opaque(kin);
         sfor<0, R1>([&](auto Rr) QT_INL {
             kk[Rr] = ldg(kin, ln.ja + Rr * T);
@@ -643,12 +663,16 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const 
     {
         const cx<R>* sa = buf + pad(ln.ja);
         const cx<R>* sb = buf + pad(ln.jb);
+        const Kin<R>* kl = LATE_KIN ? opaque(kin) : kin;
         sfor<0, R1>([&](auto Rr) QT_INL {
             a[Rr] = sa[padc<Rr * T>()];
             b[Rr] = sb[padc<Rr * T>()];
-            if constexpr (KIN) {
+            if constexpr (kEarly) {
                 a[Rr] = kmul(a[Rr], kk[Rr]);
                 b[Rr] = kmul(b[Rr], kk[R1 + Rr]);
+            } else if constexpr (KIN) {
+                a[Rr] = kmul(a[Rr], ldg(kl, ln.ja + Rr * T));
+                b[Rr] = kmul(b[Rr], ldg(kl, ln.jb + Rr * T));
             }
         });
     }

@@ -108,7 +108,11 @@ constexpr size_t dst32_buf_bytes()
 // On entry a/b hold x in the mirror layout of length N, on exit the result
 // in the same layout.  buf: LDS of dst32_buf_bytes<N, W>(); wsum: W/64
 // cx<double> of LDS; odd_step selects the FP32 twiddles' second rounding.
-template <int N, int W>
+// LEAN holds fewer values in registers across the block: each FFT pass's
+// twiddles are loaded before its exchange (not all of them once for both
+// FFTs), the mixing phases again for C^T, the kinetic factors of the even
+// outputs where they are used.
+template <int N, int W, bool LEAN = false>
 __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const Lanes<N, W>& ln_in,
                                             void* buf, cx<double>* wsum, const void* tables,
                                             const cx<double>* __restrict__ kin, bool odd_step)
@@ -212,10 +216,15 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
         cx<float>* const bx = static_cast<cx<float>*>(buf);
         cx<float>* const by = bx + padded_len<M>();
         constexpr int NX = PH::NPASS - 1;   // exchanges per FFT
-        // both FFTs take the same twiddles: loaded once
-        AllTwiddles<float, M, W, 0> tws;
-        tws.load(ln, opaque(tb.tw32));
-        fft_passes_held<float, M, W, 0>(v, ln, bx, by, tws);
+        // both FFTs take the same twiddles: loaded once (LEAN: per pass)
+        AllTwiddles<float, M, W, LEAN ? Plan<M, W>::NPASS : 0> tws;
+        const PassTwiddles<float, M, W, 0> none{};
+        auto fft = [&](cx<float>* x, cx<float>* y) QT_INL {
+            if constexpr (LEAN) fft_passes_db<float, M, W, 0>(v, ln, x, y, tb.tw32, none);
+            else fft_passes_held<float, M, W, 0>(v, ln, x, y, tws);
+        };
+        if constexpr (!LEAN) tws.load(ln, opaque(tb.tw32));
+        fft(bx, by);
         // slots n (v[r] at n = ja + rT, v[H + r] at jb + rT) times conj(K)/4
         {
             const cx<double>* kn = opaque(kin);
@@ -226,9 +235,9 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
             });
         }
         if constexpr (NX % 2 == 1)
-            fft_passes_held<float, M, W, 0>(v, ln, by, bx, tws);
+            fft(by, bx);
         else
-            fft_passes_held<float, M, W, 0>(v, ln, bx, by, tws);
+            fft(bx, by);
         // the FP64 transforms below write the whole buffer
         __syncthreads();
         // C^T: U = conj(v); a+'_j = i (e_j U_{M-j} - conj(e_j) U_j), e_j =
@@ -240,6 +249,13 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
                 const cx<float> d = p - q;
                 return mk(-d.im, d.re);
             };
+            if constexpr (LEAN) {
+                const cx<float>* wd = opaque(tb.wd);
+                sfor<0, H>([&](auto Rr) QT_INL {
+                    ea[Rr] = ldg(wd, ln.ja + Rr * T);
+                    eb[Rr] = ldg(wd, ln.jb + Rr * T);
+                });
+            }
             sfor<0, H>([&](auto Rr) QT_INL {
                 constexpr int r = Rr;
                 ap[r] = tmix(ea[r], v[H + H - 1 - r], v[r]);
@@ -263,8 +279,8 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
             cx<double> pw[H];
             load_prew<double, M, W>(pw, tb.pre64h, ln);
             cx<double>* b64 = static_cast<cx<double>*>(buf);
-            dst1<double, M, W, true>(am, bm, pw, tb.pre64h, ln, b64, wsum, opaque(tb.tw64h),
-                                     reinterpret_cast<const Kin<double>*>(kin + M));
+            dst1<double, M, W, true, LEAN>(am, bm, pw, tb.pre64h, ln, b64, wsum, opaque(tb.tw64h),
+                                           reinterpret_cast<const Kin<double>*>(kin + M));
             dst1<double, M, W, false>(am, bm, pw, tb.pre64h, ln, b64, wsum, opaque(tb.tw64h),
                                       nullptr);
         }

@@ -370,13 +370,17 @@ __device__ __forceinline__ void fill_static_phase(cx<R>* fac, const cx<R>* row,
 
 // First half-step: u <- C D u.  Returns this lane's part of sum |D u|^2 (the
 // norm the unitary block receives) when SUM; D_m - 1 goes to dm (registers,
-// for the second half-step).  With CACHE, C_m is in `fac` (this lane's
-// slots, no other lane reads them) for the second half-step: stored here,
-// or, for a static C (H::kStaticC) when STATIC, already there
-// (fill_static_phase) and read from it instead of the table.
-template <class R, int N, int W, class H, bool CACHE, bool SUM, bool STATIC = false>
+// for the second half-step), and with DML also to this lane's slots of the
+// LDS array dml (slot E at dml[E W]), from which the second half-step then
+// reads it.  With CACHE, C_m is in `fac` (this lane's slots, no other lane
+// reads them) for the second half-step: stored here, or, for a static C
+// (H::kStaticC) when STATIC, already there (fill_static_phase) and read from
+// it instead of the table.
+template <class R, int N, int W, class H, bool CACHE, bool SUM, bool STATIC = false,
+          bool DML = false>
 __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
-                                             const Lanes<N, W>& ln, cx<R>* fac, R* dm)
+                                             const Lanes<N, W>& ln, cx<R>* fac, R* dm,
+                                             R* dml = nullptr)
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
     constexpr bool kCached = CACHE && STATIC && H::kStaticC;
@@ -403,6 +407,7 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
             if constexpr (CACHE) mine[E * W] = C;
         }
         const cx<R> w = u + scale(u, dm[E]);
+        if constexpr (DML) dml[ln.t + E * W] = dm[E];
         if constexpr (SUM) acc += abs2d(w);
         u = apply_phase(w, C);
     };
@@ -415,11 +420,12 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
 }
 
 // Second half-step: u <- D C u.  Adds this lane's sum |C u|^2 to x0 (when
-// SUM0) and sum |D C u|^2 to x1.
-template <class R, int N, int W, class H, bool CACHE, bool SUM0>
+// SUM0) and sum |D C u|^2 to x1.  D_m - 1 comes from dm, or with DML from
+// the LDS slots first_half stored it in.
+template <class R, int N, int W, class H, bool CACHE, bool SUM0, bool DML = false>
 __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
                                             const Lanes<N, W>& ln, const cx<R>* fac, const R* dm,
-                                            double& x0, double& x1)
+                                            double& x0, double& x1, const R* dml = nullptr)
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
     const cx<R>* mine = fac + ln.t;
@@ -433,7 +439,8 @@ __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
         }
         const cx<R> w = apply_phase(u, C);
         if constexpr (SUM0) x0 += abs2d(w);
-        u = w + scale(w, dm[E]);
+        if constexpr (DML) u = w + scale(w, dml[ln.t + E * W]);
+        else u = w + scale(w, dm[E]);
         x1 += abs2d(u);
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
@@ -602,29 +609,63 @@ __device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, dou
 
 // ------------------------------------------------------------ FUSED -------
 
-// At least two waves per SIMD: the register budget is 256 per lane (VGPRs
-// and AGPRs together), so that the allocator never trades a register or two
-// for half the occupancy.
+// The form of a fused kernel: its LDS and its occupancy target.
+//
+// Every kernel runs at least two waves per SIMD: the register budget is then
+// 256 per lane (VGPRs and AGPRs together), so that the allocator never trades
+// a register or two for half the occupancy.
+//
+// Lean form (FP32 bulk, Munich potential, 16 values per lane, workgroups of
+// several waves): three waves per SIMD (168 registers).  Its workgroup keeps
+// no cache of the phase factors C_m (the second half-step reads the static
+// phase again and recomputes the thermal one), holds the damping factors
+// D_m - 1 in LDS instead of registers between the two half-steps, and runs
+// the transforms' LEAN form (kin_block32).  Chosen where the exchange buffer
+// and the damping factors of three waves per SIMD fit the CU's 160 KiB of
+// LDS.  Against the two-wave form with the cache it measured 5% faster
+// without the thermal phase and 9% with it at N = 2048 (W = 128), 0% and 6%
+// at N = 4096 (W = 256), and 2% and 5% slower at N = 1024 with one wave
+// per workgroup (whose transforms wait at no barrier), which keeps the
+// two-wave form.
 template <class R, int N, int W, int POT>
-__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fused_kernel(FusedArgs A)
+struct FusedForm {
+    // FP32-bulk renormalises the unitary block of every step
+    static constexpr bool kRenorm = std::is_same<R, float>::value;
+    // exchange buffer of the transforms (FP32: see dst32)
+    static constexpr size_t kBufBytes = kRenorm ? dst32_buf_bytes<N, W>()
+                                                : sizeof(cx<R>) * (size_t)padded_len<N>();
+    // block-scan and reduction scratch, work item and flag
+    static constexpr size_t kSmallBytes = (W / 64) * (sizeof(cx<double>) + 14 * sizeof(double)) + 16;
+    static constexpr int kWaves = W / 64;
+    static constexpr bool kLean = kRenorm && POT == QT_POTENTIAL_MUNICH && N / W == 16 &&
+                                  kWaves >= 2 && 12 % kWaves == 0 &&
+                                  (size_t)(12 / kWaves) * (kBufBytes + sizeof(R) * N + kSmallBytes) <=
+                                      160u * 1024u;
+    // per-lane cache of the phase factors C_m between the two half-steps of a
+    // step, kept when it still leaves room for two workgroups per CU
+    static constexpr bool kCache = !kLean && kBufBytes + sizeof(cx<R>) * N <= 80u * 1024u;
+    static constexpr int kWavesPerEU = kLean ? 3 : 2;
+};
+
+template <class R, int N, int W, int POT>
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(FusedForm<R, N, W, POT>::kWavesPerEU)))
+void fused_kernel(FusedArgs A)
 {
     using PL = Plan<N, W>;
+    using FF = FusedForm<R, N, W, POT>;
     constexpr int R1 = PL::R1, T = PL::T;
-    // FP32-bulk renormalises the unitary block of every step (see below)
-    constexpr bool kRenorm = std::is_same<R, float>::value;
-    // exchange buffer of the transforms (FP32: see dst32), block-scan scratch
-    constexpr size_t kBufBytes = kRenorm ? dst32_buf_bytes<N, W>()
-                                         : sizeof(cx<R>) * (size_t)padded_len<N>();
-    __shared__ __attribute__((aligned(16))) char buf[kBufBytes];
+    constexpr bool kRenorm = FF::kRenorm;
+    constexpr bool kLean = FF::kLean;
+    __shared__ __attribute__((aligned(16))) char buf[FF::kBufBytes];
     __shared__ cx<double> wsum[W / 64];
     __shared__ double red[14 * (W / 64)];
     __shared__ int s_item;
     __shared__ int s_zdone;
-    // per-lane cache of the phase factors C_m between the two half-steps of a
-    // step, kept when it still leaves room for two workgroups per CU
-    constexpr bool kCache = kBufBytes + sizeof(cx<R>) * N <= 80u * 1024u;
+    constexpr bool kCache = FF::kCache;
     constexpr bool kStaticCache = kCache && W > 64;
     __shared__ cx<R> fac[kCache ? N : 1];
+    // the lean form's damping factors between the half-steps
+    __shared__ R dms[kLean ? N : 1];
 
     const Lanes<N, W> ln(threadIdx.x);
     const cx<R>* tw = static_cast<const cx<R>*>(A.tw);
@@ -751,13 +792,13 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
             } else {
                 with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
                     const HalfStep<R, G, F> h{row, dr, zr, zi};
-                    n_in = first_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm, kStaticCache>(
-                        a, b, h, ls, fac, dm);
+                    n_in = first_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm, kStaticCache,
+                                      kLean>(a, b, h, ls, fac, dm, dms);
                 });
             }
             if constexpr (kRenorm) {
-                kin_block32<N, W>(a, b, ls, buf, wsum, A.tw, static_cast<const cx<double>*>(g.kin),
-                                  (n & 1) != 0);
+                kin_block32<N, W, kLean>(a, b, ls, buf, wsum, A.tw,
+                                         static_cast<const cx<double>*>(g.kin), (n & 1) != 0);
             } else {
                 const Kin<double>* kin = static_cast<const Kin<double>*>(g.kin);
                 cx<double> pw[Plan<N, W>::R1];
@@ -775,8 +816,11 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
             } else {
                 with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
                     const HalfStep<R, G, F> h{opaque(row), dr, zr, zi};
-                    second_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm>(a, b, h, ls, fac, dm,
-                                                                          x[1], x[2]);
+                    // the lean form derives the points' radii anew rather
+                    // than keeping those of the first half-step
+                    const Lanes<N, W> l2(kLean ? opaque_lane(threadIdx.x) : ls.t);
+                    second_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm, kLean>(
+                        a, b, h, l2, fac, dm, x[1], x[2], dms);
                 });
             }
             if constexpr (kRenorm) {
@@ -806,9 +850,11 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void fus
                 l = (ul < (double)l / (double)(2 * l + 1)) ? l - 1 : l + 1;
                 c = (c == QT_OCTET) ? (uc < 2.0 / 7.0 ? QT_SINGLET : QT_OCTET) : QT_OCTET;
                 log_jump(g.out, idx, n_jumps, n, l, c);
+                // (radii derived here: no register holds them across steps)
+                const Lanes<N, W> lj(opaque_lane(threadIdx.x));
                 sfor<0, R1>([&](auto Rr) QT_INL {
-                    a[Rr] = scale(a[Rr], R(ls.ja + Rr * T) * dr);
-                    b[Rr] = scale(b[Rr], R(ls.jb + Rr * T) * dr);
+                    a[Rr] = scale(a[Rr], R(lj.ja + Rr * T) * dr);
+                    b[Rr] = scale(b[Rr], R(lj.jb + Rr * T) * dr);
                 });
                 const double s2 = g.dr * block_sum<W>(sum_abs2<R, N, W>(a, b), red);
                 const R f = R(1.0 / sqrt(s2));
