@@ -158,27 +158,23 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
         // of length M.  Lanes t > 0: m = t + rT pairs with b[R1-1-r], m = T - t
         // + rT with a[R1-1-r].  Lane 0: m = rT pairs with (R1 - r) T (itself
         // at 0, where x = 0), m = W + rT with W + (R1-1-r) T.
+        // (lane 0's partners are selected per lane, not taken in a branch:
+        // the other waves of the workgroup would wait for it at the next
+        // barrier)
+        auto sel = [lane0](cx<float> p0, cx<float> p) QT_INL { return lane0 ? p0 : p; };
         cx<float> ap[H], bp[H];
         cx<double> am[H], bm[H];
         sfor<0, H>([&](auto Rr) QT_INL {
             constexpr int r = Rr;
-            ap[r] = a[r] + b[R1 - 1 - r];
-            am[r] = widen(a[r]) - widen(b[R1 - 1 - r]);
-            bp[r] = b[r] + a[R1 - 1 - r];
-            bm[r] = widen(b[r]) - widen(a[R1 - 1 - r]);
+            const cx<float> pa = sel(a[(R1 - r) % R1], b[R1 - 1 - r]);
+            const cx<float> pb = sel(b[R1 - 1 - r], a[R1 - 1 - r]);
+            ap[r] = a[r] + pa;
+            am[r] = widen(a[r]) - widen(pa);
+            bp[r] = b[r] + pb;
+            bm[r] = widen(b[r]) - widen(pb);
         });
         // a+_M = x_{N/2} (lane 0, slot a[H] since N/2 = H T)
         const cx<float> apM = a[H];
-        if (lane0) {
-            sfor<0, H>([&](auto Rr) QT_INL {
-                constexpr int r = Rr;
-                constexpr int rm = (R1 - r) % R1;
-                ap[r] = a[r] + a[rm];
-                am[r] = widen(a[r]) - widen(a[rm]);
-                bp[r] = b[r] + b[R1 - 1 - r];
-                bm[r] = widen(b[r]) - widen(b[R1 - 1 - r]);
-            });
-        }
         // C: FFT input conj(V_j) = e^{-i pi j/N} (conj(a+_{M-j}) + i
         // conj(a+_j)) in the mirror layout of length M (v[r] at j = ja + rT,
         // v[H + r] at j = jb + rT).  Lanes t > 0: the mirror M - j of ja + rT
@@ -196,20 +192,10 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
         cx<float> v[PH::P];
         sfor<0, H>([&](auto Rr) QT_INL {
             constexpr int r = Rr;
-            v[r] = ea[r] * conj_plus_iconj(bp[H - 1 - r], ap[r]);
-            v[H + r] = eb[r] * conj_plus_iconj(ap[H - 1 - r], bp[r]);
+            v[r] = ea[r] * conj_plus_iconj(sel(ap[(H - r) % H], bp[H - 1 - r]), ap[r]);
+            v[H + r] = eb[r] * conj_plus_iconj(sel(bp[H - 1 - r], ap[H - 1 - r]), bp[r]);
         });
-        if (lane0) {
-            sfor<0, H>([&](auto Rr) QT_INL {
-                constexpr int r = Rr;
-                if constexpr (r == 0) {
-                    v[0] = mk(2.0f * apM.re, -2.0f * apM.im);
-                } else {
-                    v[r] = ea[r] * conj_plus_iconj(ap[H - r], ap[r]);
-                }
-                v[H + r] = eb[r] * conj_plus_iconj(bp[H - 1 - r], bp[r]);
-            });
-        }
+        v[0] = sel(mk(2.0f * apM.re, -2.0f * apM.im), v[0]);
         // two exchange buffers (together the size of the FP64 one): the
         // first FFT exchanges through X, Y, X, ..., the second starts with
         // the other of the two that the first one ended on
@@ -258,20 +244,10 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
             }
             sfor<0, H>([&](auto Rr) QT_INL {
                 constexpr int r = Rr;
-                ap[r] = tmix(ea[r], v[H + H - 1 - r], v[r]);
-                bp[r] = tmix(eb[r], v[H - 1 - r], v[H + r]);
+                ap[r] = tmix(ea[r], sel(v[(H - r) % H], v[H + H - 1 - r]), v[r]);
+                bp[r] = tmix(eb[r], sel(v[H + H - 1 - r], v[H - 1 - r]), v[H + r]);
             });
-            if (lane0) {
-                sfor<0, H>([&](auto Rr) QT_INL {
-                    constexpr int r = Rr;
-                    if constexpr (r == 0) {
-                        ap[0] = mk(0.0f, 0.0f);
-                    } else {
-                        ap[r] = tmix(ea[r], v[H - r], v[r]);
-                    }
-                    bp[r] = tmix(eb[r], v[H + H - 1 - r], v[H + r]);
-                });
-            }
+            ap[0] = sel(mk(0.0f, 0.0f), ap[0]);
         }
         const cx<float> pM = mk(2.0f * v[0].re, -2.0f * v[0].im);
         // D, the kinetic factors of the even outputs, D^T = D, in FP64
@@ -287,28 +263,24 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
         // B^T: x_m = a+'_m + a-'_m, x_{N-m} = a+'_m - a-'_m, x_{N/2} = a+'_M
         auto plus = [](cx<float> p, cx<double> q) QT_INL { return narrow(widen(p) + q); };
         auto minus = [](cx<float> p, cx<double> q) QT_INL { return narrow(widen(p) - q); };
-        if (lane0) {
-            sfor<0, H>([&](auto Rr) QT_INL {
-                constexpr int r = Rr;
-                if constexpr (r == 0) {
-                    a[0] = mk(0.0f, 0.0f);
-                } else {
-                    a[r] = plus(ap[r], am[r]);
-                    a[R1 - r] = minus(ap[r], am[r]);
-                }
-                b[r] = plus(bp[r], bm[r]);
-                b[R1 - 1 - r] = minus(bp[r], bm[r]);
-            });
-            a[H] = pM;
-        } else {
-            sfor<0, H>([&](auto Rr) QT_INL {
-                constexpr int r = Rr;
-                a[r] = plus(ap[r], am[r]);
-                b[R1 - 1 - r] = minus(ap[r], am[r]);
-                b[r] = plus(bp[r], bm[r]);
-                a[R1 - 1 - r] = minus(bp[r], bm[r]);
-            });
-        }
+        // every lane: x_m = a+'_m + a-'_m at its slots r < H of a and b; the
+        // mirrors x_{N-m} = a+'_m - a-'_m go to b[R1-1-r] and a[R1-1-r], on
+        // lane 0 to a[R1-r] and b[R1-1-r] (a[H] = x_{N/2}, a[0] = x_0 = 0)
+        cx<float> ma[H], mb[H];
+        sfor<0, H>([&](auto Rr) QT_INL {
+            constexpr int r = Rr;
+            a[r] = plus(ap[r], am[r]);
+            b[r] = plus(bp[r], bm[r]);
+            ma[r] = minus(ap[r], am[r]);
+            mb[r] = minus(bp[r], bm[r]);
+        });
+        a[0] = sel(mk(0.0f, 0.0f), a[0]);
+        sfor<H, R1>([&](auto Ii) QT_INL {
+            constexpr int i = Ii;
+            if constexpr (i == H) a[i] = sel(pM, mb[R1 - 1 - i]);
+            else a[i] = sel(ma[R1 - i], mb[R1 - 1 - i]);
+            b[i] = sel(mb[R1 - 1 - i], ma[R1 - 1 - i]);
+        });
     }
 }
 
