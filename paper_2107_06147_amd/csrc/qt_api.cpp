@@ -480,10 +480,28 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
         std::vector<double> d(4 * (size_t)M + 4 * (size_t)N);
         fill(M, &d[0], &d[2 * (size_t)M]);
         fill(N, &d[4 * (size_t)M], &d[4 * (size_t)M + 2 * (size_t)N]);
+        // the FFT twiddles of length M once more as level tables (rounding a
+        // | rounding b): level L = 4, 8, ..., M holds exp(-2 pi i r k / L),
+        // r = 1..7, k < L/2, row by row (qt_device.hpp, level_index); the
+        // same values as the table above, rows contiguous in k
+        const size_t nl = (size_t)level_table_len(M);
+        const size_t l0 = 2 * 4 * (size_t)M;   // in f, after the first block
+        f.resize(l0 + 2 * 2 * nl);
+        for (int L = 4; L <= M; L *= 2)
+            for (int r = 1; r <= 7; ++r)
+                for (int k = 0; k < L / 2; ++k) {
+                    const int m = (int)(((int64_t)r * k) % L);
+                    const size_t e = (size_t)level_index(L, r, k);
+                    two(l0 / 2 + e, l0 / 2 + nl + e, std::cos(2.0 * kPi * m / L),
+                        -std::sin(2.0 * kPi * m / L));
+                }
+        const size_t f0 = 4 * 2 * (size_t)M;   // floats of the first FP32 block
         QT_HIP(hipMalloc(&t.tw, f.size() * 4 + d.size() * 8));
-        QT_HIP(hipMemcpy(t.tw, f.data(), f.size() * 4, hipMemcpyHostToDevice));
-        QT_HIP(hipMemcpy(static_cast<char*>(t.tw) + f.size() * 4, d.data(), d.size() * 8,
+        QT_HIP(hipMemcpy(t.tw, f.data(), f0 * 4, hipMemcpyHostToDevice));
+        QT_HIP(hipMemcpy(static_cast<char*>(t.tw) + f0 * 4, d.data(), d.size() * 8,
                          hipMemcpyHostToDevice));
+        QT_HIP(hipMemcpy(static_cast<char*>(t.tw) + f0 * 4 + d.size() * 8, f.data() + f0,
+                         (f.size() - f0) * 4, hipMemcpyHostToDevice));
         t.prew = nullptr;
     } else {
         std::vector<double> tw(2 * (size_t)N), sn(2 * (size_t)N);

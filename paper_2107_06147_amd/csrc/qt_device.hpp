@@ -17,6 +17,7 @@
 #include <stdint.h>
 #include <type_traits>
 
+#include "qt_internal.h"
 #include "qt_philox.h"
 
 namespace qt {
@@ -289,6 +290,24 @@ struct PassTwiddles {
             });
         }
     }
+    // The same from a level table: level L = NS RAD (4, 8, ..., N) holds
+    // w_L^{r k} = exp(-2 pi i r k / L) at entry level_index(L, r, k) (r =
+    // 1..7, k < L/2), so that for each r the lanes of a pass read
+    // consecutive entries (the natural table at r k N/L spreads them over up
+    // to 8 r times as many cache lines).
+    __device__ __forceinline__ void load_level(const Lanes<N, W>& ln, const cx<R>* lev)
+    {
+        if constexpr (NS > 1) {
+            constexpr int L = NS * RAD;
+            sfor<0, B>([&](auto Q) QT_INL {
+                const int k = bfly(ln, Q) & (NS - 1);
+                cx<R>* wq = w + Q * (RAD - 1);
+                sfor<1, RAD>([&](auto Rr) QT_INL {
+                    wq[Rr - 1] = ldg(lev, (uint32_t)(level_index(L, Rr, 0) + k));
+                });
+            });
+        }
+    }
 };
 
 // Butterflies of pass p: twiddle (passes after the first), then the DFT of
@@ -366,10 +385,16 @@ struct AllTwiddles {
         cur.load(ln, tw);
         rest.load(ln, tw);
     }
+    __device__ __forceinline__ void load_level(const Lanes<N, W>& ln, const cx<R>* lev)
+    {
+        cur.load_level(ln, lev);
+        rest.load_level(ln, lev);
+    }
 };
 template <class R, int N, int W, int p>
 struct AllTwiddles<R, N, W, p, true> {
     __device__ __forceinline__ void load(const Lanes<N, W>&, const cx<R>*) {}
+    __device__ __forceinline__ void load_level(const Lanes<N, W>&, const cx<R>*) {}
 };
 
 // fft_passes with the twiddles already in registers, and two exchange
@@ -390,19 +415,20 @@ __device__ __forceinline__ void fft_passes_held(cx<R>* v, const Lanes<N, W>& ln,
 }
 
 // fft_passes_held with two exchange buffers as there, but each pass's
-// twiddles loaded before the exchange that precedes it instead of held for
-// the whole FFT (fewer registers; their latency overlaps the exchange).
+// twiddles loaded (from a level table) before the exchange that precedes it
+// instead of held for the whole FFT (fewer registers; their latency
+// overlaps the exchange).
 template <class R, int N, int W, int p>
 __device__ __forceinline__ void fft_passes_db(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf,
-                                              cx<R>* buf2, const cx<R>* __restrict__ tw,
+                                              cx<R>* buf2, const cx<R>* __restrict__ lev,
                                               const PassTwiddles<R, N, W, p>& cur)
 {
     fft_pass<R, N, W, p>(v, cur);
     if constexpr (p + 1 < Plan<N, W>::NPASS) {
         PassTwiddles<R, N, W, p + 1> nxt;
-        nxt.load(ln, opaque(tw));
+        nxt.load_level(ln, opaque(lev));
         fft_exchange<R, N, W, p>(v, ln, buf);
-        fft_passes_db<R, N, W, p + 1>(v, ln, buf2, buf, tw, nxt);
+        fft_passes_db<R, N, W, p + 1>(v, ln, buf2, buf, lev, nxt);
     }
 }
 

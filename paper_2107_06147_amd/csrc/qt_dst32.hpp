@@ -33,10 +33,12 @@
 // Tables (one block, see ensure_tables): FP32 [FFT twiddles of length M |
 // e^{-i pi j/N}, j < M | the same two in a second rounding], then FP64
 // [FFT twiddles of length M | DST-I weights of length M | FFT twiddles of
-// length N | DST-I weights of length N].  The two roundings of the FP32
-// factors alternate step by step: their error, otherwise the same every
-// step, then largely cancels between consecutive steps.  The kinetic factors
-// are in the slot order of kin_block32 (below).
+// length N | DST-I weights of length N], then the FP32 FFT twiddles of
+// length M as level tables (PassTwiddles::load_level) in the two roundings.
+// The two roundings of the FP32 factors alternate step by step: their
+// error, otherwise the same every step, then largely cancels between
+// consecutive steps.  The kinetic factors are in the slot order of
+// kin_block32 (below).
 #pragma once
 #include "qt_device.hpp"
 
@@ -51,6 +53,7 @@ struct Dst32Tables {
     const cx<double>* pre64h;  // DST-I weights, length M
     const cx<double>* tw64;    // FFT twiddles, length N
     const cx<double>* pre64;   // DST-I weights, length N
+    const cx<float>* lev32;    // FFT twiddles of length M, level table
     // the FP32 factors in rounding b when `second` (see ensure_tables)
     __device__ __forceinline__ Dst32Tables(const void* base, bool second)
     {
@@ -61,6 +64,7 @@ struct Dst32Tables {
         pre64h = tw64h + M;
         tw64 = pre64h + M;
         pre64 = tw64 + N;
+        lev32 = reinterpret_cast<const cx<float>*>(pre64 + N) + (second ? level_table_len(M) : 0);
     }
 };
 
@@ -206,10 +210,10 @@ __device__ __forceinline__ void kin_block32(cx<float>* a, cx<float>* b, const La
         AllTwiddles<float, M, W, LEAN ? Plan<M, W>::NPASS : 0> tws;
         const PassTwiddles<float, M, W, 0> none{};
         auto fft = [&](cx<float>* x, cx<float>* y) QT_INL {
-            if constexpr (LEAN) fft_passes_db<float, M, W, 0>(v, ln, x, y, tb.tw32, none);
+            if constexpr (LEAN) fft_passes_db<float, M, W, 0>(v, ln, x, y, tb.lev32, none);
             else fft_passes_held<float, M, W, 0>(v, ln, x, y, tws);
         };
-        if constexpr (!LEAN) tws.load(ln, opaque(tb.tw32));
+        if constexpr (!LEAN) tws.load_level(ln, opaque(tb.lev32));
         fft(bx, by);
         // slots n (v[r] at n = ja + rT, v[H + r] at jb + rT) times conj(K)/4
         {

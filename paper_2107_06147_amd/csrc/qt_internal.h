@@ -52,6 +52,13 @@ struct GroupDesc {
 // smallest norm).
 constexpr int32_t kFlagZeroth = 1 << 16;
 
+// Entry of exp(-2 pi i r k / L) in a level table of FFT twiddles (built by
+// the host, read by PassTwiddles::load_level): levels L = 4, 8, ... in turn,
+// each 7 rows r = 1..7 of L/2 entries k.  A table for FFTs of length up to n
+// holds level_table_len(n) entries.
+constexpr int level_index(int L, int r, int k) { return 7 * (L - 4) / 2 + (r - 1) * (L / 2) + k; }
+constexpr int level_table_len(int n) { return level_index(2 * n, 1, 0); }
+
 struct FusedArgs {
     const GroupDesc* groups;
     const int32_t*   item_group;
