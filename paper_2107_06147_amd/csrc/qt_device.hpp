@@ -50,10 +50,12 @@ template <class R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b)
     return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
 }
 template <class R> __device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return mk(a.re * s, a.im * s); }
-template <class R> __device__ __forceinline__ double abs2d(cx<R> a)
+// acc + |a|^2 in FP64 as two fused multiply-adds (the squares of FP32
+// values are exact in FP64)
+template <class R> __device__ __forceinline__ void add_abs2(double& acc, cx<R> a)
 {
-    double x = (double)a.re, y = (double)a.im;
-    return x * x + y * y;
+    const double x = (double)a.re, y = (double)a.im;
+    acc = fma(y, y, fma(x, x, acc));
 }
 
 // Hides a pointer's value from the optimiser so that table loads through it

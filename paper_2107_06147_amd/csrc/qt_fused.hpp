@@ -408,7 +408,7 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
         }
         const cx<R> w = u + scale(u, dm[E]);
         if constexpr (DML) dml[ln.t + E * W] = dm[E];
-        if constexpr (SUM) acc += abs2d(w);
+        if constexpr (SUM) add_abs2(acc, w);
         u = apply_phase(w, C);
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
@@ -438,10 +438,10 @@ __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
             h.factors(m, h.preload(m), unused, C);
         }
         const cx<R> w = apply_phase(u, C);
-        if constexpr (SUM0) x0 += abs2d(w);
+        if constexpr (SUM0) add_abs2(x0, w);
         if constexpr (DML) u = w + scale(w, dml[ln.t + E * W]);
         else u = w + scale(w, dm[E]);
-        x1 += abs2d(u);
+        add_abs2(x1, u);
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
         apply(ln.ja + Rr * T, a[Rr], std::integral_constant<int, Rr>{});
@@ -482,7 +482,10 @@ __device__ __forceinline__ double sum_abs2(const cx<R>* a, const cx<R>* b)
 {
     constexpr int R1 = Plan<N, W>::R1;
     double acc = 0.0;
-    sfor<0, R1>([&](auto Rr) QT_INL { acc += abs2d(a[Rr]) + abs2d(b[Rr]); });
+    sfor<0, R1>([&](auto Rr) QT_INL {
+        add_abs2(acc, a[Rr]);
+        add_abs2(acc, b[Rr]);
+    });
     return acc;
 }
 
