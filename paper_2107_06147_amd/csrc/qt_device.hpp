@@ -111,16 +111,20 @@ __device__ __forceinline__ int opaque_lane(int t)
     return t;
 }
 
-// LDS index with one pad element every 16 (spreads power-of-two strides
-// over the banks).
-__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+// LDS index with one pad element every 2^S (spreads power-of-two strides
+// over the banks); S = 4 unless a kernel asks for another.
+template <int S = 4>
+__device__ __forceinline__ int pad(int i) { return i + (i >> S); }
 // pad(base + C) for a compile-time C, as a constant offset from pad(base).
-// Valid when the low four bits of base and C do not carry into bit 4, which
-// holds for every access below: each one is base + C with base & 15 and C
-// together below 16, or C a multiple of 16 (all sizes are powers of two).
-// The offset then goes into the LDS instruction's immediate field.
-template <int C> constexpr int padc() { return C + (C >> 4); }
-template <int N> constexpr int padded_len() { return N + N / 16; }
+// Valid when the low S bits of base and C do not carry into bit S, which
+// holds for every access below for S = 3, 4 and 5: each one is base + C
+// with base mod 2^S and C mod 2^S together below 2^S (all sizes, strides
+// and radices are powers of two; the exchange writes pair j mod NS with
+// multiples of NS, the sine transform's post-processing and prefix sum an
+// even base with the odd offset 1, a multiple of 2 CH with offsets below
+// 2 CH).  The offset then goes into the LDS instruction's immediate field.
+template <int C, int S = 4> constexpr int padc() { return C + (C >> S); }
+template <int N, int S = 4> constexpr int padded_len() { return N + (N >> S); }
 
 // cos(2 pi k / 64), k = 0..63
 constexpr double kCos64[64] = {
@@ -334,7 +338,7 @@ __device__ __forceinline__ void fft_pass(cx<R>* v, const PassTwiddles<R, N, W, p
 // The exchange after pass p through LDS into the input layout of pass p + 1:
 // write, barrier, read.  Butterfly j of a pass with stride NS reads
 // x[j + r N/RAD] and writes y[(j/NS) NS RAD + j%NS + r NS].
-template <class R, int N, int W, int p>
+template <class R, int N, int W, int p, int S = 4>
 __device__ __forceinline__ void fft_exchange(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf)
 {
     using PL = Plan<N, W>;
@@ -344,8 +348,8 @@ __device__ __forceinline__ void fft_exchange(cx<R>* v, const Lanes<N, W>& ln, cx
     sfor<0, TW::B>([&](auto Q) QT_INL {
         constexpr int q = Q;
         const int j = TW::bfly(ln, q);
-        cx<R>* dst = buf + pad((j / NS) * NS * RAD + (j & (NS - 1)));
-        sfor<0, RAD>([&](auto Rr) QT_INL { dst[padc<Rr * NS>()] = v[q * RAD + Rr]; });
+        cx<R>* dst = buf + pad<S>((j / NS) * NS * RAD + (j & (NS - 1)));
+        sfor<0, RAD>([&](auto Rr) QT_INL { dst[padc<Rr * NS, S>()] = v[q * RAD + Rr]; });
     });
     __syncthreads();
     constexpr int RAD2 = PL::radix(p + 1);
@@ -353,15 +357,15 @@ __device__ __forceinline__ void fft_exchange(cx<R>* v, const Lanes<N, W>& ln, cx
     sfor<0, B2>([&](auto Q) QT_INL {
         constexpr int q = Q;
         const int j = PassTwiddles<R, N, W, p + 1>::bfly(ln, q);
-        const cx<R>* src = buf + pad(j);
-        sfor<0, RAD2>([&](auto Rr) QT_INL { v[q * RAD2 + Rr] = src[padc<Rr * (N / RAD2)>()]; });
+        const cx<R>* src = buf + pad<S>(j);
+        sfor<0, RAD2>([&](auto Rr) QT_INL { v[q * RAD2 + Rr] = src[padc<Rr * (N / RAD2), S>()]; });
     });
 }
 
 // The passes p.. of the FFT.  The next pass's twiddles are loaded before
 // the exchange, so that their latency overlaps it; a barrier follows each
 // exchange's read, so that the next exchange may overwrite the buffer.
-template <class R, int N, int W, int p>
+template <class R, int N, int W, int p, int S = 4>
 __device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R>* buf,
                                            const cx<R>* __restrict__ tw,
                                            const PassTwiddles<R, N, W, p>& cur)
@@ -370,9 +374,9 @@ __device__ __forceinline__ void fft_passes(cx<R>* v, const Lanes<N, W>& ln, cx<R
     if constexpr (p + 1 < Plan<N, W>::NPASS) {
         PassTwiddles<R, N, W, p + 1> nxt;
         nxt.load(ln, opaque(tw));
-        fft_exchange<R, N, W, p>(v, ln, buf);
+        fft_exchange<R, N, W, p, S>(v, ln, buf);
         __syncthreads();
-        fft_passes<R, N, W, p + 1>(v, ln, buf, tw, nxt);
+        fft_passes<R, N, W, p + 1, S>(v, ln, buf, tw, nxt);
     }
 }
 
@@ -578,7 +582,7 @@ __device__ __forceinline__ void load_prew(cx<R>* pw, const cx<R>* prew, const La
 // same layout.  The kinetic factors are loaded before the prefix sum, whose
 // exchanges hide their latency, or, LATE_KIN, where they are used (fewer
 // registers held across the sum).
-template <class R, int N, int W, bool KIN, bool LATE_KIN = false>
+template <class R, int N, int W, bool KIN, bool LATE_KIN = false, int S = 4>
 __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const cx<R>* prew,
                                      const Lanes<N, W>& ln_in, cx<R>* buf, cx<R>* wsum,
                                      const cx<R>* __restrict__ tw,
@@ -623,7 +627,7 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const 
     }
     {
         PassTwiddles<R, N, W, 0> none;
-        fft_passes<R, N, W, 0>(v, ln, buf, tw, none);
+        fft_passes<R, N, W, 0, S>(v, ln, buf, tw, none);
     }
     // post-processing: pairs (k, N-k), even outputs F_{2k} and differences
     // D_k for k < N/2 (Y here is half the FFT of y)
@@ -632,15 +636,15 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const 
         constexpr int r = Rr;
         {   // k = ja + r T, N - k = jb + (R1-1-r) T
             const cx<R> y = v[r], yp = v[2 * R1 - 1 - r];
-            cx<R>* dst = buf + pad(2 * ln.ja);
-            dst[padc<2 * r * T>()] = mul_i(y - yp);
-            dst[padc<2 * r * T>() + 1] = y + yp;
+            cx<R>* dst = buf + pad<S>(2 * ln.ja);
+            dst[padc<2 * r * T, S>()] = mul_i(y - yp);
+            dst[padc<2 * r * T, S>() + 1] = y + yp;
         }
         {   // k = jb + r T, N - k = ja + (R1-1-r) T
             const cx<R> y = v[R1 + r], yp = v[R1 - 1 - r];
-            cx<R>* dst = buf + pad(2 * ln.jb);
-            dst[padc<2 * r * T>()] = mul_i(y - yp);
-            dst[padc<2 * r * T>() + 1] = y + yp;
+            cx<R>* dst = buf + pad<S>(2 * ln.jb);
+            dst[padc<2 * r * T, S>()] = mul_i(y - yp);
+            dst[padc<2 * r * T, S>() + 1] = y + yp;
         }
     });
     if (lane0) {
@@ -650,15 +654,15 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const 
             constexpr int r = Rr;
             {
                 const cx<R> y = v[r], yp = v[(R1 - r) % R1];
-                cx<R>* dst = buf + pad(2 * ln.ja);
-                dst[padc<2 * r * T>()] = mul_i(y - yp);
-                dst[padc<2 * r * T>() + 1] = y + yp;
+                cx<R>* dst = buf + pad<S>(2 * ln.ja);
+                dst[padc<2 * r * T, S>()] = mul_i(y - yp);
+                dst[padc<2 * r * T, S>() + 1] = y + yp;
             }
             {
                 const cx<R> y = v[R1 + r], yp = v[2 * R1 - 1 - r];
-                cx<R>* dst = buf + pad(2 * ln.jb);
-                dst[padc<2 * r * T>()] = mul_i(y - yp);
-                dst[padc<2 * r * T>() + 1] = y + yp;
+                cx<R>* dst = buf + pad<S>(2 * ln.jb);
+                dst[padc<2 * r * T, S>()] = mul_i(y - yp);
+                dst[padc<2 * r * T, S>() + 1] = y + yp;
             }
         });
     }
@@ -676,25 +680,25 @@ __device__ __forceinline__ void dst1(cx<R>* a, cx<R>* b, const cx<R>* pw, const 
     __syncthreads();
     // prefix sum of D_k over k = 0..N/2-1: contiguous chunks per lane
     constexpr int CH = N / (2 * W);
-    const cx<R> d0 = buf[pad(1)];
+    const cx<R> d0 = buf[pad<S>(1)];
     cx<R> pre[CH];
     cx<R> run = mk(R(0), R(0));
-    cx<R>* chunk = buf + pad(2 * CH * ln.t);
+    cx<R>* chunk = buf + pad<S>(2 * CH * ln.t);
     sfor<0, CH>([&](auto I) QT_INL {
-        run = run + chunk[padc<2 * I + 1>()];
+        run = run + chunk[padc<2 * I + 1, S>()];
         pre[I] = run;
     });
     const cx<R> off = block_exclusive_scan<W>(run, wsum) - scale(d0, R(0.5));
-    sfor<0, CH>([&](auto I) QT_INL { chunk[padc<2 * I + 1>()] = pre[I] + off; });
+    sfor<0, CH>([&](auto I) QT_INL { chunk[padc<2 * I + 1, S>()] = pre[I] + off; });
     __syncthreads();
     auto kmul = [&](cx<R> F, const Kin<R>& k) QT_INL { return F * k.v; };
     {
-        const cx<R>* sa = buf + pad(ln.ja);
-        const cx<R>* sb = buf + pad(ln.jb);
+        const cx<R>* sa = buf + pad<S>(ln.ja);
+        const cx<R>* sb = buf + pad<S>(ln.jb);
         const Kin<R>* kl = LATE_KIN ? opaque(kin) : kin;
         sfor<0, R1>([&](auto Rr) QT_INL {
-            a[Rr] = sa[padc<Rr * T>()];
-            b[Rr] = sb[padc<Rr * T>()];
+            a[Rr] = sa[padc<Rr * T, S>()];
+            b[Rr] = sb[padc<Rr * T, S>()];
             if constexpr (kEarly) {
                 a[Rr] = kmul(a[Rr], kk[Rr]);
                 b[Rr] = kmul(b[Rr], kk[R1 + Rr]);
