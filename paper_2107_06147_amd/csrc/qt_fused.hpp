@@ -160,7 +160,7 @@ __device__ __forceinline__ float expm1_small(float x)
 __device__ __forceinline__ double expm1_small(double x) { return expm1(x); }
 
 // FP32 sin and cos on |x| <= pi/4: Taylor series to x^9 and x^10
-// (remainders < 2e-9).  FP64 uses the library function.
+// (remainders < 2e-9).
 __device__ __forceinline__ void sincos_small(float x, float* s, float* c)
 {
     const float x2 = x * x;
@@ -176,7 +176,32 @@ __device__ __forceinline__ void sincos_small(float x, float* s, float* c)
     cp = fmaf(cp, x2, -0.5f);
     *c = fmaf(cp, x2, 1.0f);
 }
-__device__ __forceinline__ void sincos_small(double x, double* s, double* c) { sincos(x, s, c); }
+// FP64 sin and cos on |x| <= pi/4: Taylor series to x^17 and x^18
+// (remainders below 2e-19 and 5e-21 there), cheaper than the library
+// functions' range reduction.
+__device__ __forceinline__ void sincos_small(double x, double* s, double* c)
+{
+    const double x2 = x * x;
+    double sp = 1.0 / 355687428096000.0;                  // 1/17!
+    sp = fma(sp, -x2, 1.0 / 1307674368000.0);             // 1/15!
+    sp = fma(sp, -x2, 1.0 / 6227020800.0);                // 1/13!
+    sp = fma(sp, -x2, 1.0 / 39916800.0);                  // 1/11!
+    sp = fma(sp, -x2, 1.0 / 362880.0);                    // 1/9!
+    sp = fma(sp, -x2, 1.0 / 5040.0);                      // 1/7!
+    sp = fma(sp, -x2, 1.0 / 120.0);                       // 1/5!
+    sp = fma(sp, -x2, 1.0 / 6.0);                         // 1/3!
+    *s = fma(-sp * x2, x, x);
+    double cp = 1.0 / 6402373705728000.0;                 // 1/18!
+    cp = fma(cp, -x2, 1.0 / 20922789888000.0);            // 1/16!
+    cp = fma(cp, -x2, 1.0 / 87178291200.0);               // 1/14!
+    cp = fma(cp, -x2, 1.0 / 479001600.0);                 // 1/12!
+    cp = fma(cp, -x2, 1.0 / 3628800.0);                   // 1/10!
+    cp = fma(cp, -x2, 1.0 / 40320.0);                     // 1/8!
+    cp = fma(cp, -x2, 1.0 / 720.0);                       // 1/6!
+    cp = fma(cp, -x2, 1.0 / 24.0);                        // 1/4!
+    cp = fma(cp, -x2, 0.5);                               // 1/2!
+    *c = fma(-cp, x2, 1.0);
+}
 
 // FP32 sin(x) and cos(x) - 1 on |x| <= pi/4, cos - 1 without the 1 (see
 // qsincos_m1).
@@ -618,36 +643,43 @@ __device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, dou
 // 256 per lane (VGPRs and AGPRs together), so that the allocator never trades
 // a register or two for half the occupancy.
 //
-// Lean form (FP32 bulk, Munich potential, 16 values per lane, workgroups of
-// several waves): three waves per SIMD (168 registers).  Its workgroup keeps
-// no cache of the phase factors C_m (the second half-step reads the static
-// phase again and recomputes the thermal one), holds the damping factors
-// D_m - 1 in LDS instead of registers between the two half-steps, and runs
-// the transforms' LEAN form (kin_block32).  Chosen where the exchange buffer
+// Lean form (Munich potential, workgroups of several waves, FP32 bulk with
+// 16 values per lane or FP64 with 8): three waves per SIMD (168 registers).
+// Its workgroup keeps no cache of the phase factors C_m (the second
+// half-step reads the static phase again and recomputes the thermal one),
+// holds the damping factors D_m - 1 in LDS instead of registers between the
+// two half-steps, and runs the transforms' lean forms (kin_block32 LEAN,
+// dst1 LATE_KIN).  Chosen where the exchange buffer (one pad element in 16)
 // and the damping factors of three waves per SIMD fit the CU's 160 KiB of
 // LDS.  Against the two-wave form with the cache it measured 5% faster
-// without the thermal phase and 9% with it at N = 2048 (W = 128), 0% and 6%
-// at N = 4096 (W = 256), and 2% and 5% slower at N = 1024 with one wave
-// per workgroup (whose transforms wait at no barrier), which keeps the
-// two-wave form.
+// without the thermal phase and 9% with it at N = 2048 (FP32, W = 128), 0%
+// and 6% at N = 4096 (FP32, W = 256), 6% and 15% at N = 2048 (FP64,
+// W = 256); and 2% and 5% slower at N = 1024 (FP32) with one wave per
+// workgroup (whose transforms wait at no barrier), which keeps the two-wave
+// form.
 template <class R, int N, int W, int POT>
 struct FusedForm {
     // FP32-bulk renormalises the unitary block of every step
     static constexpr bool kRenorm = std::is_same<R, float>::value;
-    // LDS padding of the FP64 form's transforms: one element in 8 (fewer
-    // bank conflicts of its 16-byte exchanges than one in 16: 0.70 against
-    // 1.19 conflict cycles per active LDS cycle at N = 2048, 2% faster)
-    static constexpr int kPadS = 3;
-    // exchange buffer of the transforms (FP32: see dst32)
-    static constexpr size_t kBufBytes = kRenorm ? dst32_buf_bytes<N, W>()
-                                                : sizeof(cx<R>) * (size_t)padded_len<N, kPadS>();
     // block-scan and reduction scratch, work item and flag
     static constexpr size_t kSmallBytes = (W / 64) * (sizeof(cx<double>) + 14 * sizeof(double)) + 16;
     static constexpr int kWaves = W / 64;
-    static constexpr bool kLean = kRenorm && POT == QT_POTENTIAL_MUNICH && N / W == 16 &&
+    // exchange buffer of the transforms with one pad element in 16 (FP32:
+    // see dst32)
+    static constexpr size_t kBuf16 = kRenorm ? dst32_buf_bytes<N, W>()
+                                             : sizeof(cx<R>) * (size_t)padded_len<N, 4>();
+    static constexpr bool kLean = POT == QT_POTENTIAL_MUNICH && N / W == (kRenorm ? 16 : 8) &&
                                   kWaves >= 2 && 12 % kWaves == 0 &&
-                                  (size_t)(12 / kWaves) * (kBufBytes + sizeof(R) * N + kSmallBytes) <=
+                                  (size_t)(12 / kWaves) * (kBuf16 + sizeof(R) * N + kSmallBytes) <=
                                       160u * 1024u;
+    // LDS padding of the two-wave FP64 form's transforms: one element in 8
+    // (fewer bank conflicts of its 16-byte exchanges than one in 16: 0.70
+    // against 1.19 conflict cycles per active LDS cycle at N = 2048, 2%
+    // faster); the lean forms keep one in 16 (their LDS is at the limit)
+    static constexpr int kPadS = (!kRenorm && !kLean) ? 3 : 4;
+    // exchange buffer of the transforms
+    static constexpr size_t kBufBytes = kRenorm ? dst32_buf_bytes<N, W>()
+                                                : sizeof(cx<R>) * (size_t)padded_len<N, kPadS>();
     // per-lane cache of the phase factors C_m between the two half-steps of a
     // step, kept when it still leaves room for two workgroups per CU
     static constexpr bool kCache = !kLean && kBufBytes + sizeof(cx<R>) * N <= 80u * 1024u;
@@ -782,9 +814,10 @@ void fused_kernel(FusedArgs A)
             const R zr = R(-0.5 * g.dt * cc * kh * T3);
             const R zi = R(-0.5 * g.dt * cc * g.gamma_hat * T3);
             const cx<R>* row = opaque(phase_row<R, N>(g, l, c));
-            // FP64 always takes the library functions
-            const bool fast = !kRenorm || (fabs(-0.5 * g.dt * cc * kh * T3) * xmax <= 0.5 &&
-                                           fabs(-0.5 * g.dt * cc * g.gamma_hat * T3) * xmax <= 0.78);
+            // (FP64: the damping always from the library's expm1, the thermal
+            // phase from the series only in range)
+            const bool fast = fabs(-0.5 * g.dt * cc * kh * T3) * xmax <= 0.5 &&
+                              fabs(-0.5 * g.dt * cc * g.gamma_hat * T3) * xmax <= 0.78;
 
             R dm[Plan<N, W>::P];
             double n_in = 0.0;
@@ -812,7 +845,7 @@ void fused_kernel(FusedArgs A)
                 load_prew<double, N, W>(pw, prew, ls);
                 cx<double>* bd = reinterpret_cast<cx<double>*>(buf);
                 const cx<double>* tw_n = opaque(tw);
-                dst1<double, N, W, true, false, FF::kPadS>(a, b, pw, prew, ls, bd, wsum, tw_n, kin);
+                dst1<double, N, W, true, kLean, FF::kPadS>(a, b, pw, prew, ls, bd, wsum, tw_n, kin);
                 dst1<double, N, W, false, false, FF::kPadS>(a, b, pw, prew, ls, bd, wsum, opaque(tw_n),
                                                             nullptr);
             }
