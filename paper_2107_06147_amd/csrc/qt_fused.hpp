@@ -144,7 +144,8 @@ __device__ __forceinline__ const cx<R>* phase_row(const GroupDesc& g, int l, int
 }
 
 // FP32 exp(x) - 1 on |x| <= 1/2: the Taylor series to x^8 (remainder
-// < 2e-8 relative).  FP64 uses the library function.
+// < 2e-8 relative); FP64 to x^15 (remainder < 5e-17 relative, two units of
+// the FP64 roundoff in all).
 __device__ __forceinline__ float expm1_small(float x)
 {
     float p = 1.0f / 40320.0f;
@@ -157,7 +158,25 @@ __device__ __forceinline__ float expm1_small(float x)
     p = fmaf(p, x, 1.0f);
     return p * x;
 }
-__device__ __forceinline__ double expm1_small(double x) { return expm1(x); }
+__device__ __forceinline__ double expm1_small(double x)
+{
+    double p = 1.0 / 1307674368000.0;                     // 1/15!
+    p = fma(p, x, 1.0 / 87178291200.0);                   // 1/14!
+    p = fma(p, x, 1.0 / 6227020800.0);                    // 1/13!
+    p = fma(p, x, 1.0 / 479001600.0);                     // 1/12!
+    p = fma(p, x, 1.0 / 39916800.0);                      // 1/11!
+    p = fma(p, x, 1.0 / 3628800.0);                       // 1/10!
+    p = fma(p, x, 1.0 / 362880.0);                        // 1/9!
+    p = fma(p, x, 1.0 / 40320.0);                         // 1/8!
+    p = fma(p, x, 1.0 / 5040.0);                          // 1/7!
+    p = fma(p, x, 1.0 / 720.0);                           // 1/6!
+    p = fma(p, x, 1.0 / 120.0);                           // 1/5!
+    p = fma(p, x, 1.0 / 24.0);                            // 1/4!
+    p = fma(p, x, 1.0 / 6.0);                             // 1/3!
+    p = fma(p, x, 0.5);                                   // 1/2!
+    p = fma(p, x, 1.0);
+    return p * x;
+}
 
 // FP32 sin and cos on |x| <= pi/4: Taylor series to x^9 and x^10
 // (remainders < 2e-9).
@@ -814,8 +833,7 @@ void fused_kernel(FusedArgs A)
             const R zr = R(-0.5 * g.dt * cc * kh * T3);
             const R zi = R(-0.5 * g.dt * cc * g.gamma_hat * T3);
             const cx<R>* row = opaque(phase_row<R, N>(g, l, c));
-            // (FP64: the damping always from the library's expm1, the thermal
-            // phase from the series only in range)
+            // (both precisions: the series only in range)
             const bool fast = fabs(-0.5 * g.dt * cc * kh * T3) * xmax <= 0.5 &&
                               fabs(-0.5 * g.dt * cc * g.gamma_hat * T3) * xmax <= 0.78;
 
