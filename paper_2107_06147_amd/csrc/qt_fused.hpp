@@ -261,6 +261,17 @@ __device__ __forceinline__ cx<float> phase_product(cx<float> a, cx<float> b)
     return a + b + a * b;
 }
 
+// FP64 factors outside the series' ranges (a rare path: large time steps or
+// temperatures): the library functions, in functions of their own so that
+// their constants do not take registers in the time loop.
+__device__ __noinline__ double expm1_far(double x) { return expm1(x); }
+__device__ __noinline__ double2 sincos_far(double x)
+{
+    double s, c;
+    sincos(x, &s, &c);
+    return make_double2(s, c);
+}
+
 // The half-step factor exp(-i V_eff(r_m) dt/2) of one time step is
 //   P_m exp(z r_m^2),   z = zr + i zi = -(dt/2) c (kappa + i gamma) T^3,
 // c = 1/2 (singlet) or 7/32 (octet), P_m the static phase (table row).  It is
@@ -289,7 +300,9 @@ struct HalfStep {
     }
     __device__ __forceinline__ R em1(R x2) const
     {
-        return FAST ? expm1_small(zr * x2) : qexpm1(zr * x2);
+        if constexpr (FAST) return expm1_small(zr * x2);
+        else if constexpr (std::is_same<R, double>::value) return expm1_far(zr * x2);
+        else return qexpm1(zr * x2);
     }
     __device__ __forceinline__ cx<R> static_phase(int m) const { return ldg(row, m); }
     __device__ __forceinline__ cx<R> phase(cx<R> p, R x2) const
@@ -300,8 +313,13 @@ struct HalfStep {
                 if constexpr (FAST) sincos_small_m1(zi * x2, &s, &c);
                 else qsincos_m1(zi * x2, &s, &c);
             } else {
-                if constexpr (FAST) sincos_small(zi * x2, &s, &c);
-                else qsincos(zi * x2, &s, &c);
+                if constexpr (FAST) {
+                    sincos_small(zi * x2, &s, &c);
+                } else {
+                    const double2 sc = sincos_far(zi * x2);
+                    s = sc.x;
+                    c = sc.y;
+                }
             }
             return phase_product(p, mk(c, s));
         } else {
