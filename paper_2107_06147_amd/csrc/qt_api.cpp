@@ -455,9 +455,12 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
     qt_context::Tables t;
     if (f32) {
         // the FP32 sine transform (split form, qt_dst32.hpp), one block:
-        // FP32 [FFT twiddles of length M = N/2, rounding a | exp(-i pi j/N),
-        // j < M, rounding a | the same two in rounding b], FP64 [FFT
-        // twiddles, DST-I weights of length M | the same of length N].
+        // FP32 [exp(-i pi j/N), j < M = N/2, rounding a | the same in
+        // rounding b], FP64 [FFT twiddles, DST-I weights of length M | the
+        // same of length N], then the FP32 FFT twiddles of length M as level
+        // tables (rounding a | rounding b): level L = 4, 8, ..., M holds
+        // exp(-2 pi i r k / L), r = 1..7, k < L/2, row by row (level_index),
+        // so that the lanes of an FFT pass read consecutive entries.
         // Rounding a is to nearest; b rounds 2w - a, so that (a + b)/2 lies
         // closer to w than either.  The kernel alternates the two step by
         // step: the rounding error of these factors, the same every step
@@ -466,36 +469,28 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
         // (The neighbour of modulus closest to 1 would trade the modulus
         // error for a larger phase error, which adds up the same way.)
         const int M = N / 2;
-        std::vector<float> f(8 * (size_t)M);
+        const size_t nl = (size_t)level_table_len(M);
+        const size_t f0 = 4 * (size_t)M;        // floats of the mixing phases
+        std::vector<float> f(f0 + 4 * nl);
         auto two = [&](size_t ia, size_t ib, double c, double s) {
             f[2 * ia] = (float)c;
             f[2 * ia + 1] = (float)s;
             f[2 * ib] = (float)(2.0 * c - (double)f[2 * ia]);
             f[2 * ib + 1] = (float)(2.0 * s - (double)f[2 * ia + 1]);
         };
-        for (int m = 0; m < M; ++m) {
-            two(m, 2 * (size_t)M + m, std::cos(2.0 * kPi * m / M), -std::sin(2.0 * kPi * m / M));
-            two((size_t)M + m, 3 * (size_t)M + m, std::cos(kPi * m / N), -std::sin(kPi * m / N));
-        }
-        std::vector<double> d(4 * (size_t)M + 4 * (size_t)N);
-        fill(M, &d[0], &d[2 * (size_t)M]);
-        fill(N, &d[4 * (size_t)M], &d[4 * (size_t)M + 2 * (size_t)N]);
-        // the FFT twiddles of length M once more as level tables (rounding a
-        // | rounding b): level L = 4, 8, ..., M holds exp(-2 pi i r k / L),
-        // r = 1..7, k < L/2, row by row (qt_device.hpp, level_index); the
-        // same values as the table above, rows contiguous in k
-        const size_t nl = (size_t)level_table_len(M);
-        const size_t l0 = 2 * 4 * (size_t)M;   // in f, after the first block
-        f.resize(l0 + 2 * 2 * nl);
+        for (int m = 0; m < M; ++m)
+            two(m, (size_t)M + m, std::cos(kPi * m / N), -std::sin(kPi * m / N));
         for (int L = 4; L <= M; L *= 2)
             for (int r = 1; r <= 7; ++r)
                 for (int k = 0; k < L / 2; ++k) {
                     const int m = (int)(((int64_t)r * k) % L);
                     const size_t e = (size_t)level_index(L, r, k);
-                    two(l0 / 2 + e, l0 / 2 + nl + e, std::cos(2.0 * kPi * m / L),
+                    two(f0 / 2 + e, f0 / 2 + nl + e, std::cos(2.0 * kPi * m / L),
                         -std::sin(2.0 * kPi * m / L));
                 }
-        const size_t f0 = 4 * 2 * (size_t)M;   // floats of the first FP32 block
+        std::vector<double> d(4 * (size_t)M + 4 * (size_t)N);
+        fill(M, &d[0], &d[2 * (size_t)M]);
+        fill(N, &d[4 * (size_t)M], &d[4 * (size_t)M + 2 * (size_t)N]);
         QT_HIP(hipMalloc(&t.tw, f.size() * 4 + d.size() * 8));
         QT_HIP(hipMemcpy(t.tw, f.data(), f0 * 4, hipMemcpyHostToDevice));
         QT_HIP(hipMemcpy(static_cast<char*>(t.tw) + f0 * 4, d.data(), d.size() * 8,

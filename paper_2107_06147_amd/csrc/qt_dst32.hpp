@@ -30,15 +30,14 @@
 // A step's kinetic block applies S K S; the second transform runs as the
 // transpose of the first (kin_block32), so neither leaves its slots.
 //
-// Tables (one block, see ensure_tables): FP32 [FFT twiddles of length M |
-// e^{-i pi j/N}, j < M | the same two in a second rounding], then FP64
-// [FFT twiddles of length M | DST-I weights of length M | FFT twiddles of
-// length N | DST-I weights of length N], then the FP32 FFT twiddles of
-// length M as level tables (PassTwiddles::load_level) in the two roundings.
-// The two roundings of the FP32 factors alternate step by step: their
-// error, otherwise the same every step, then largely cancels between
-// consecutive steps.  The kinetic factors are in the slot order of
-// kin_block32 (below).
+// Tables (one block, see ensure_tables): FP32 [e^{-i pi j/N}, j < M | the
+// same in a second rounding], then FP64 [FFT twiddles of length M | DST-I
+// weights of length M | FFT twiddles of length N | DST-I weights of length
+// N], then the FP32 FFT twiddles of length M as level tables
+// (PassTwiddles::load_level) in the two roundings.  The two roundings of the
+// FP32 factors alternate step by step: their error, otherwise the same
+// every step, then largely cancels between consecutive steps.  The kinetic
+// factors are in the slot order of kin_block32 (below).
 #pragma once
 #include "qt_device.hpp"
 
@@ -47,8 +46,7 @@ namespace qt {
 template <int N>
 struct Dst32Tables {
     static constexpr int M = N / 2;
-    const cx<float>* tw32;     // FFT twiddles, length M (rounding a or b)
-    const cx<float>* wd;       // e^{-i pi j / N}, j < M
+    const cx<float>* wd;       // e^{-i pi j / N}, j < M (rounding a or b)
     const cx<double>* tw64h;   // FFT twiddles, length M
     const cx<double>* pre64h;  // DST-I weights, length M
     const cx<double>* tw64;    // FFT twiddles, length N
@@ -58,9 +56,8 @@ struct Dst32Tables {
     __device__ __forceinline__ Dst32Tables(const void* base, bool second)
     {
         const char* p = static_cast<const char*>(base);
-        tw32 = reinterpret_cast<const cx<float>*>(p) + (second ? 2 * M : 0);
-        wd = reinterpret_cast<const cx<float>*>(p) + (second ? 3 * M : M);
-        tw64h = reinterpret_cast<const cx<double>*>(p + 4 * (size_t)M * sizeof(cx<float>));
+        wd = reinterpret_cast<const cx<float>*>(p) + (second ? M : 0);
+        tw64h = reinterpret_cast<const cx<double>*>(p + 2 * (size_t)M * sizeof(cx<float>));
         pre64h = tw64h + M;
         tw64 = pre64h + M;
         pre64 = tw64 + N;
