@@ -255,13 +255,15 @@ struct Lanes {
 };
 
 // Twiddle factors of pass p for this lane's butterflies (none for the first
-// pass, whose stride is 1): w^{r k}, r = 1..RAD-1, for butterfly k.  FP32
-// reads each from the table (its rounding is what limits the FP32 form's
-// accuracy).  FP64 reads w^k only and forms the other powers as products of
-// two lower ones, w^{r k} = w^{h k} w^{(r-h) k} with h the largest power of
-// two below r (r/2 for a power of two): at most three products deep, a few
-// units of the FP64 roundoff, and one table read where there were RAD - 1
-// (table reads, not arithmetic, are what the transforms wait for).
+// pass, whose stride is 1): w^{r k}, r = 1..RAD-1, for butterfly k, w =
+// exp(-2 pi i / L), L = NS RAD.  FP32 reads each from a level table
+// (load_level; its rounding is what limits the FP32 form's accuracy).  FP64
+// reads w^k only, from the natural table of length N at k N/L (load), and
+// forms the other powers as products of two lower ones, w^{r k} = w^{h k}
+// w^{(r-h) k} with h the largest power of two below r (r/2 for a power of
+// two): at most three products deep, a few units of the FP64 roundoff, and
+// one table read where there were RAD - 1 (table reads, not arithmetic, are
+// what the transforms wait for).
 template <class R, int N, int W, int p>
 struct PassTwiddles {
     using PL = Plan<N, W>;
@@ -277,22 +279,17 @@ struct PassTwiddles {
     }
     __device__ __forceinline__ void load(const Lanes<N, W>& ln, const cx<R>* tw)
     {
+        static_assert(sizeof(R) == sizeof(double), "FP32 twiddles come from level tables");
         if constexpr (NS > 1) {
             sfor<0, B>([&](auto Q) QT_INL {
                 const int k = bfly(ln, Q) & (NS - 1);
                 cx<R>* wq = w + Q * (RAD - 1);   // wq[r - 1] = w^{r k}
-                if constexpr (sizeof(R) == sizeof(double)) {
-                    wq[0] = ldg(tw, k * (N / (NS * RAD)));
-                    sfor<2, RAD>([&](auto Rr) QT_INL {
-                        constexpr int r = Rr;
-                        constexpr int h = (r & (r - 1)) ? (1 << ilog2(r)) : r / 2;
-                        wq[r - 1] = wq[h - 1] * wq[r - h - 1];
-                    });
-                } else {
-                    sfor<1, RAD>([&](auto Rr) QT_INL {
-                        wq[Rr - 1] = ldg(tw, Rr * k * (N / (NS * RAD)));
-                    });
-                }
+                wq[0] = ldg(tw, k * (N / (NS * RAD)));
+                sfor<2, RAD>([&](auto Rr) QT_INL {
+                    constexpr int r = Rr;
+                    constexpr int h = (r & (r - 1)) ? (1 << ilog2(r)) : r / 2;
+                    wq[r - 1] = wq[h - 1] * wq[r - h - 1];
+                });
             });
         }
     }
@@ -386,11 +383,6 @@ template <class R, int N, int W, int p, bool END = (p >= Plan<N, W>::NPASS)>
 struct AllTwiddles {
     PassTwiddles<R, N, W, p> cur;
     AllTwiddles<R, N, W, p + 1> rest;
-    __device__ __forceinline__ void load(const Lanes<N, W>& ln, const cx<R>* tw)
-    {
-        cur.load(ln, tw);
-        rest.load(ln, tw);
-    }
     __device__ __forceinline__ void load_level(const Lanes<N, W>& ln, const cx<R>* lev)
     {
         cur.load_level(ln, lev);
@@ -399,7 +391,6 @@ struct AllTwiddles {
 };
 template <class R, int N, int W, int p>
 struct AllTwiddles<R, N, W, p, true> {
-    __device__ __forceinline__ void load(const Lanes<N, W>&, const cx<R>*) {}
     __device__ __forceinline__ void load_level(const Lanes<N, W>&, const cx<R>*) {}
 };
 

@@ -687,8 +687,9 @@ __device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, dou
 // holds the damping factors D_m - 1 in LDS instead of registers between the
 // two half-steps, and runs the transforms' lean forms (kin_block32 LEAN,
 // dst1 LATE_KIN).  Chosen where the exchange buffer (one pad element in 16)
-// and the damping factors of three waves per SIMD fit the CU's 160 KiB of
-// LDS.  Against the two-wave form with the cache it measured 5% faster
+// and the damping factors of three waves per SIMD fit in 156 of the CU's
+// 160 KiB of LDS (a variant at 158 KiB, accepted by the occupancy query,
+// ran 15% slower, as if a workgroup less fitted).  Against the two-wave form with the cache it measured 5% faster
 // without the thermal phase and 9% with it at N = 2048 (FP32, W = 128), 0%
 // and 6% at N = 4096 (FP32, W = 256), 6% and 15% at N = 2048 (FP64,
 // W = 256); and 2% and 5% slower at N = 1024 (FP32) with one wave per
@@ -708,7 +709,7 @@ struct FusedForm {
     static constexpr bool kLean = POT == QT_POTENTIAL_MUNICH && N / W == (kRenorm ? 16 : 8) &&
                                   kWaves >= 2 && 12 % kWaves == 0 &&
                                   (size_t)(12 / kWaves) * (kBuf16 + sizeof(R) * N + kSmallBytes) <=
-                                      160u * 1024u;
+                                      156u * 1024u;
     // LDS padding of the two-wave FP64 form's transforms: one element in 8
     // (fewer bank conflicts of its 16-byte exchanges than one in 16: 0.70
     // against 1.19 conflict cycles per active LDS cycle at N = 2048, 2%
