@@ -220,6 +220,22 @@ def test_every_kernel_variant(N):
 C2_SAMPLE = [0, 1, 2047, 4095]
 
 
+# Trajectories per CU of the benchmark's variants: the three-wave forms
+# (LDS and 168 registers sized for three waves per SIMD) and a two-wave one.
+# A change that grows their LDS or registers past the budget would cost a
+# third of the resident trajectories without failing any other test.
+@pytest.mark.parametrize("N,prec,w,per_cu", [(2048, F32, 128, 6), (4096, F32, 256, 3),
+                                            (2048, F64, 256, 3), (1024, F64, 128, 6),
+                                            (1024, F32, 64, 8)])
+def test_forms_keep_their_occupancy(N, prec, w, per_cu):
+    c = qt.Context(0)
+    try:
+        c.plan_set(N, prec, w)
+        assert c.plan(N, prec) == (w, per_cu)
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("prec,form", [(F64, FUSED), (F32, FUSED), (F64, PLAIN)])
 def test_c2_full_batch_sampled(ctx, prec, form):
     """4096 trajectories at N=2048 in the benchmark's launch configuration,
