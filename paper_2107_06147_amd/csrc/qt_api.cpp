@@ -459,8 +459,9 @@ qt_status ensure_tables(qt_context* ctx, int prec, int N, qt_context::Tables* ou
         // rounding b], FP64 [FFT twiddles, DST-I weights of length M | the
         // same of length N], then the FP32 FFT twiddles of length M as level
         // tables (rounding a | rounding b): level L = 4, 8, ..., M holds
-        // exp(-2 pi i r k / L), r = 1..7, k < L/2, row by row (level_index),
-        // so that the lanes of an FFT pass read consecutive entries.
+        // exp(-2 pi i r k / L), r = 1..7, k < L/2, in pair rows
+        // (level_index), so that the lanes of an FFT pass read consecutive
+        // entries.
         // Rounding a is to nearest; b rounds 2w - a, so that (a + b)/2 lies
         // closer to w than either.  The kernel alternates the two step by
         // step: the rounding error of these factors, the same every step
@@ -615,7 +616,8 @@ constexpr int kLTab = 255;
 
 // exp(-i (dt/2) [V_coulomb(r_m) + l(l+1)/(M r_m^2)]) for l = 0..kLTab and
 // both colours (appendix "Munich potential"), rows [(2 l + c) N + m]; FP32
-// rows hold the factor minus one, (cos - 1, sin), each part rounded once.
+// rows hold the factor minus one, (cos - 1, sin), each part rounded once, in
+// mirror pairs (mirror_pair_index).
 static void phase_table(const HostBatch& h, bool f32, char* dst)
 {
     const int N = h.phys.N;
@@ -637,7 +639,7 @@ static void phase_table(const HostBatch& h, bool f32, char* dst)
                 }
                 if (f32) {
                     // the factor minus one (the kernel applies u + (C - 1) u)
-                    float* d = reinterpret_cast<float*>(dst) + 2 * (row + m);
+                    float* d = reinterpret_cast<float*>(dst) + 2 * (row + mirror_pair_index(N, m));
                     d[0] = (float)cm1;
                     d[1] = (float)sn;
                 } else {

@@ -87,6 +87,16 @@ __device__ __forceinline__ cx<R> ldg(const cx<R>* p, uint32_t i)
     z.im = v.y;
     return z;
 }
+// Two consecutive table elements i, i + 1 (i even: 16-byte aligned) in one load.
+__device__ __forceinline__ void ldg_pair(const cx<float>* p, uint32_t i, cx<float>& x, cx<float>& y)
+{
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *(const QT_GLOBAL v4*)((const QT_GLOBAL char*)p + i * (uint32_t)sizeof(cx<float>));
+    x.re = v.x;
+    x.im = v.y;
+    y.re = v.z;
+    y.im = v.w;
+}
 // Kinetic factor of one momentum (one complex value).
 template <class R> struct Kin { cx<R> v; };
 template <class R>
@@ -295,18 +305,27 @@ struct PassTwiddles {
     }
     // The same from a level table: level L = NS RAD (4, 8, ..., N) holds
     // w_L^{r k} = exp(-2 pi i r k / L) at entry level_index(L, r, k) (r =
-    // 1..7, k < L/2), so that for each r the lanes of a pass read
-    // consecutive entries (the natural table at r k N/L spreads them over up
-    // to 8 r times as many cache lines).
+    // 1..7, k < L/2): the powers r = 1, 2 (3, 4 and 5, 6) of one k side by
+    // side, one 16-byte load, the pairs of consecutive k consecutive, so that
+    // the lanes of a pass read consecutive entries (the natural table at r k
+    // N/L spreads them over up to 8 r times as many cache lines) with half
+    // the load instructions of one per power.
     __device__ __forceinline__ void load_level(const Lanes<N, W>& ln, const cx<R>* lev)
     {
+        static_assert(RAD <= 8, "the level tables hold the powers r <= 7");
         if constexpr (NS > 1) {
             constexpr int L = NS * RAD;
             sfor<0, B>([&](auto Q) QT_INL {
                 const int k = bfly(ln, Q) & (NS - 1);
                 cx<R>* wq = w + Q * (RAD - 1);
                 sfor<1, RAD>([&](auto Rr) QT_INL {
-                    wq[Rr - 1] = ldg(lev, (uint32_t)(level_index(L, Rr, 0) + k));
+                    constexpr int r = Rr;
+                    if constexpr (r % 2 == 1) {
+                        if constexpr (r + 1 < RAD)
+                            ldg_pair(lev, (uint32_t)level_index(L, r, k), wq[r - 1], wq[r]);
+                        else
+                            wq[r - 1] = ldg(lev, (uint32_t)level_index(L, r, k));
+                    }
                 });
             });
         }
@@ -429,6 +448,33 @@ __device__ __forceinline__ void fft_passes_db(cx<R>* v, const Lanes<N, W>& ln, c
     }
 }
 
+// The values of this lane's slots (slot r < R1: point ja + rT, slot R1 + r:
+// jb + rT) from an FP32 table of length N in mirror pairs: entry e < N/2 (16
+// bytes) holds the values at e and N - e (at 0 and N/2 for e = 0).  Every
+// lane t > 0 reads the pairs (t + rT, with its slot b[R1-1-r]) and (T - t +
+// rT, with a[R1-1-r]), r < R1/2, at consecutive entries with its
+// neighbours: half the loads of one per point, each as coalesced.  Lane 0
+// (points rT and W + rT) finds the partners of its upper slots in the other
+// entry of the two, selected per lane.
+template <int N, int W>
+__device__ __forceinline__ void load_mirror_pairs(const cx<float>* tab, const Lanes<N, W>& ln,
+                                                  cx<float>* v)
+{
+    constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T, Q = R1 / 2;
+    const bool lane0 = ln.t == 0;
+    cx<float> ax[Q], ay[Q], bx[Q], by[Q];
+    sfor<0, Q>([&](auto Rr) QT_INL {
+        ldg_pair(tab, 2u * (uint32_t)(ln.ja + Rr * T), ax[Rr], ay[Rr]);
+        ldg_pair(tab, 2u * (uint32_t)(ln.jb + Rr * T), bx[Rr], by[Rr]);
+    });
+    sfor<0, Q>([&](auto Rr) QT_INL {
+        constexpr int r = Rr;
+        v[r] = ax[r];
+        v[R1 + r] = bx[r];
+        v[R1 - 1 - r] = lane0 ? ay[(r + 1) % Q] : by[r];
+        v[2 * R1 - 1 - r] = lane0 ? by[r] : ay[r];
+    });
+}
 // ------------------------------------------------------- reductions -------
 
 // Cross-lane moves with the data-parallel-primitives (DPP) modifier: a VALU

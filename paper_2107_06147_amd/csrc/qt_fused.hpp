@@ -136,7 +136,7 @@ __device__ __forceinline__ void block_sum_vec(double* x, double* red)
 // it in FP64 for every (l, colour) with l <= l_tab, shared by all
 // trajectories of a grid; a half-step reads the row of its (l, colour) (L1/L2
 // resident: few rows are in use at a time).  FP32 rows hold the factor minus
-// one (see apply_phase).
+// one (see apply_phase), in mirror pairs (see load_mirror_pairs).
 template <class R, int N>
 __device__ __forceinline__ const cx<R>* phase_row(const GroupDesc& g, int l, int c)
 {
@@ -291,6 +291,8 @@ struct HalfStep {
     // without the thermal phase C_m is the static phase: the same every step
     // until a jump changes (l, colour), so a cache of it stays valid
     static constexpr bool kStaticC = !GAMMA;
+    // FP32 rows hold mirror pairs (see load_mirror_pairs)
+    static constexpr bool kPairRows = std::is_same<R, float>::value;
     const cx<R>* row;
     R dr, zr, zi;
     __device__ __forceinline__ R r2(int m) const
@@ -353,6 +355,7 @@ constexpr int kPhiFine = 4096, kPhiCoarse = 16256;   // intervals
 template <class R>
 struct HalfStepKSU {
     static constexpr bool kStaticC = false;
+    static constexpr bool kPairRows = false;
     const cx<R>* phi_tab;     // (phi, phi'): kPhiFine + 1 fine, then kPhiCoarse + 1
     R dr, half_dt, md, cI, cent, vsb;
     __device__ __forceinline__ cx<R> preload(int) const { return mk(R(0), R(0)); }
@@ -424,10 +427,16 @@ __device__ __forceinline__ void fill_static_phase(cx<R>* fac, const cx<R>* row,
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
     cx<R>* mine = fac + ln.t;
-    sfor<0, R1>([&](auto Rr) QT_INL {
-        mine[Rr * W] = ldg(row, ln.ja + Rr * T);
-        mine[(R1 + Rr) * W] = ldg(row, ln.jb + Rr * T);
-    });
+    if constexpr (std::is_same<R, float>::value) {
+        cx<float> pr[2 * R1];
+        load_mirror_pairs<N, W>(row, ln, pr);
+        sfor<0, 2 * R1>([&](auto E) QT_INL { mine[E * W] = pr[E]; });
+    } else {
+        sfor<0, R1>([&](auto Rr) QT_INL {
+            mine[Rr * W] = ldg(row, ln.ja + Rr * T);
+            mine[(R1 + Rr) * W] = ldg(row, ln.jb + Rr * T);
+        });
+    }
 }
 
 // First half-step: u <- C D u.  Returns this lane's part of sum |D u|^2 (the
@@ -450,15 +459,19 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
     cx<R>* mine = fac + ln.t;
     // table (or cache) data first: every load in flight at once
     cx<R> pr[2 * R1];
-    sfor<0, R1>([&](auto Rr) QT_INL {
-        if constexpr (kCached) {
-            pr[Rr] = mine[Rr * W];
-            pr[R1 + Rr] = mine[(R1 + Rr) * W];
-        } else {
-            pr[Rr] = h.preload(ln.ja + Rr * T);
-            pr[R1 + Rr] = h.preload(ln.jb + Rr * T);
-        }
-    });
+    if constexpr (!kCached && H::kPairRows) {
+        load_mirror_pairs<N, W>(h.row, ln, pr);
+    } else {
+        sfor<0, R1>([&](auto Rr) QT_INL {
+            if constexpr (kCached) {
+                pr[Rr] = mine[Rr * W];
+                pr[R1 + Rr] = mine[(R1 + Rr) * W];
+            } else {
+                pr[Rr] = h.preload(ln.ja + Rr * T);
+                pr[R1 + Rr] = h.preload(ln.jb + Rr * T);
+            }
+        });
+    }
     auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
         cx<R> C;
         if constexpr (kCached) {
@@ -491,13 +504,16 @@ __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
 {
     constexpr int R1 = Plan<N, W>::R1, T = Plan<N, W>::T;
     const cx<R>* mine = fac + ln.t;
+    constexpr bool kPairs = !CACHE && H::kPairRows;
+    cx<R> pr[kPairs ? 2 * R1 : 1];
+    if constexpr (kPairs) load_mirror_pairs<N, W>(h.row, ln, pr);
     auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
         cx<R> C;
         if constexpr (CACHE) {
             C = mine[E * W];
         } else {
             R unused;
-            h.factors(m, h.preload(m), unused, C);
+            h.factors(m, kPairs ? pr[E] : h.preload(m), unused, C);
         }
         const cx<R> w = apply_phase(u, C);
         if constexpr (SUM0) add_abs2(x0, w);

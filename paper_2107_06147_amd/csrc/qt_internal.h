@@ -54,10 +54,21 @@ constexpr int32_t kFlagZeroth = 1 << 16;
 
 // Entry of exp(-2 pi i r k / L) in a level table of FFT twiddles (built by
 // the host, read by PassTwiddles::load_level): levels L = 4, 8, ... in turn,
-// each 7 rows r = 1..7 of L/2 entries k.  A table for FFTs of length up to n
-// holds level_table_len(n) entries.
-constexpr int level_index(int L, int r, int k) { return 7 * (L - 4) / 2 + (r - 1) * (L / 2) + k; }
+// each 7 L/2 entries: three rows of L/2 pairs (r, r + 1) = (1, 2), (3, 4),
+// (5, 6), the pair of k at 2k, then the row r = 7 of L/2 entries k.  A table
+// for FFTs of length up to n holds level_table_len(n) entries.
+constexpr int level_index(int L, int r, int k)
+{
+    return 7 * (L - 4) / 2 + (r <= 6 ? ((r - 1) >> 1) * L + 2 * k + ((r - 1) & 1) : 3 * L + k);
+}
 constexpr int level_table_len(int n) { return level_index(2 * n, 1, 0); }
+// Entry of the value at point m (m < n) of a table of length n held in
+// mirror pairs (entry e < n/2: the values at e and n - e, at 0 and n/2 for
+// e = 0; read by load_mirror_pairs), in complex elements.
+constexpr int mirror_pair_index(int n, int m)
+{
+    return m < n / 2 ? 2 * m : (m == n / 2 ? 1 : 2 * (n - m) + 1);
+}
 
 struct FusedArgs {
     const GroupDesc* groups;
