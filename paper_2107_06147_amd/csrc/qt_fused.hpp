@@ -495,9 +495,11 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
 }
 
 // Second half-step: u <- D C u.  Adds this lane's sum |C u|^2 to x0 (when
-// SUM0) and sum |D C u|^2 to x1.  D_m - 1 comes from dm, or with DML from
-// the LDS slots first_half stored it in.
-template <class R, int N, int W, class H, bool CACHE, bool SUM0, bool DML = false>
+// SUM0) and sum |D C u|^2 to x1.  D_m - 1 comes from dm, with DML from the
+// LDS slots first_half stored it in, with RECOMP from the factor itself
+// (computed again as in first_half, the same value).
+template <class R, int N, int W, class H, bool CACHE, bool SUM0, bool DML = false,
+          bool RECOMP = false>
 __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
                                             const Lanes<N, W>& ln, const cx<R>* fac, const R* dm,
                                             double& x0, double& x1, const R* dml = nullptr)
@@ -518,6 +520,7 @@ __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
         const cx<R> w = apply_phase(u, C);
         if constexpr (SUM0) add_abs2(x0, w);
         if constexpr (DML) u = w + scale(w, dml[ln.t + E * W]);
+        else if constexpr (RECOMP) u = w + scale(w, h.damping(m));
         else u = w + scale(w, dm[E]);
         add_abs2(x1, u);
     };
@@ -700,12 +703,13 @@ __device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, dou
 // 16 values per lane or FP64 with 8): three waves per SIMD (168 registers).
 // Its workgroup keeps no cache of the phase factors C_m (the second
 // half-step reads the static phase again and recomputes the thermal one),
-// holds the damping factors D_m - 1 in LDS instead of registers between the
-// two half-steps, and runs the transforms' lean forms (kin_block32 LEAN,
-// dst1 LATE_KIN).  Chosen where the exchange buffer (one pad element in 16)
-// and the damping factors of three waves per SIMD fit in 156 of the CU's
-// 160 KiB of LDS (a variant at 158 KiB, accepted by the occupancy query,
-// ran 15% slower, as if a workgroup less fitted).  Against the two-wave form with the cache it measured 5% faster
+// does not keep the damping factors D_m - 1 in registers between the two
+// half-steps (FP32 holds them in LDS; FP64 recomputes them, which its VALU
+// has room for, and gives the LDS to the padding of its transforms instead),
+// and runs the transforms' lean forms (kin_block32 LEAN, dst1 LATE_KIN).
+// Chosen where the LDS of three waves per SIMD fits in 156 of the CU's 160
+// KiB (a variant at 158 KiB, accepted by the occupancy query, ran 15%
+// slower, as if a workgroup less fitted).  Against the two-wave form with the cache it measured 5% faster
 // without the thermal phase and 9% with it at N = 2048 (FP32, W = 128), 0%
 // and 6% at N = 4096 (FP32, W = 256), 6% and 15% at N = 2048 (FP64,
 // W = 256); and 2% and 5% slower at N = 1024 (FP32) with one wave per
@@ -722,15 +726,22 @@ struct FusedForm {
     // see dst32)
     static constexpr size_t kBuf16 = kRenorm ? dst32_buf_bytes<N, W>()
                                              : sizeof(cx<R>) * (size_t)padded_len<N, 4>();
+    // LDS of a lean workgroup: FP32 the exchange buffer (one pad element in
+    // 16) and the damping factors, FP64 the exchange buffer with one pad
+    // element in 8
+    static constexpr size_t kLeanLds =
+        (kRenorm ? kBuf16 + sizeof(R) * N : sizeof(cx<R>) * (size_t)padded_len<N, 3>()) +
+        kSmallBytes;
     static constexpr bool kLean = POT == QT_POTENTIAL_MUNICH && N / W == (kRenorm ? 16 : 8) &&
                                   kWaves >= 2 && 12 % kWaves == 0 &&
-                                  (size_t)(12 / kWaves) * (kBuf16 + sizeof(R) * N + kSmallBytes) <=
-                                      156u * 1024u;
-    // LDS padding of the two-wave FP64 form's transforms: one element in 8
-    // (fewer bank conflicts of its 16-byte exchanges than one in 16: 0.70
-    // against 1.19 conflict cycles per active LDS cycle at N = 2048, 2%
-    // faster); the lean forms keep one in 16 (their LDS is at the limit)
-    static constexpr int kPadS = (!kRenorm && !kLean) ? 3 : 4;
+                                  (size_t)(12 / kWaves) * kLeanLds <= 156u * 1024u;
+    // LDS padding of the FP64 forms' transforms: one element in 8 (fewer
+    // bank conflicts of their 16-byte exchanges than one in 16: 0.70 against
+    // 1.19 conflict cycles per active LDS cycle at N = 2048, 2% faster); FP32
+    // one in 16 (its LDS is at the limit)
+    static constexpr int kPadS = kRenorm ? 4 : 3;
+    // the damping factors between the half-steps in LDS (lean FP32)
+    static constexpr bool kDmLds = kLean && kRenorm;
     // exchange buffer of the transforms
     static constexpr size_t kBufBytes = kRenorm ? dst32_buf_bytes<N, W>()
                                                 : sizeof(cx<R>) * (size_t)padded_len<N, kPadS>();
@@ -757,8 +768,8 @@ void fused_kernel(FusedArgs A)
     constexpr bool kCache = FF::kCache;
     constexpr bool kStaticCache = kCache && W > 64;
     __shared__ cx<R> fac[kCache ? N : 1];
-    // the lean form's damping factors between the half-steps
-    __shared__ R dms[kLean ? N : 1];
+    // the lean FP32 form's damping factors between the half-steps
+    __shared__ R dms[FF::kDmLds ? N : 1];
 
     const Lanes<N, W> ln(threadIdx.x);
     const cx<R>* tw = static_cast<const cx<R>*>(A.tw);
@@ -886,7 +897,7 @@ void fused_kernel(FusedArgs A)
                 with_factor_kind(has_gamma, fast, [&](auto G, auto F) QT_INL {
                     const HalfStep<R, G, F> h{row, dr, zr, zi};
                     n_in = first_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm, kStaticCache,
-                                      kLean>(a, b, h, ls, fac, dm, dms);
+                                      FF::kDmLds>(a, b, h, ls, fac, dm, dms);
                 });
             }
             if constexpr (kRenorm) {
@@ -913,8 +924,8 @@ void fused_kernel(FusedArgs A)
                     // the lean form derives the points' radii anew rather
                     // than keeping those of the first half-step
                     const Lanes<N, W> l2(kLean ? opaque_lane(threadIdx.x) : ls.t);
-                    second_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm, kLean>(
-                        a, b, h, l2, fac, dm, x[1], x[2], dms);
+                    second_half<R, N, W, HalfStep<R, G, F>, kCache, kRenorm, FF::kDmLds,
+                                kLean && !kRenorm>(a, b, h, l2, fac, dm, x[1], x[2], dms);
                 });
             }
             if constexpr (kRenorm) {
