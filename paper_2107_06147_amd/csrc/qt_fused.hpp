@@ -439,11 +439,35 @@ __device__ __forceinline__ void fill_static_phase(cx<R>* fac, const cx<R>* row,
     }
 }
 
+// The damping factors of the slots (2g, 2g + 1, R1 + 2g, R1 + 2g + 1) of
+// lane t as one 16-byte LDS entry, at dml[4 (t + g W)]: one LDS write and
+// one read per four factors.
+template <int W, class R>
+__device__ __forceinline__ void store_dm4(R* dml, int t, int g, R d0, R d1, R d2, R d3)
+{
+    typedef R v4 __attribute__((ext_vector_type(4)));
+    v4 v;
+    v.x = d0;
+    v.y = d1;
+    v.z = d2;
+    v.w = d3;
+    reinterpret_cast<v4*>(dml)[t + g * W] = v;
+}
+template <int W, class R>
+__device__ __forceinline__ void load_dm4(const R* dml, int t, int g, R* d)
+{
+    typedef R v4 __attribute__((ext_vector_type(4)));
+    const v4 v = reinterpret_cast<const v4*>(dml)[t + g * W];
+    d[0] = v.x;
+    d[1] = v.y;
+    d[2] = v.z;
+    d[3] = v.w;
+}
+
 // First half-step: u <- C D u.  Returns this lane's part of sum |D u|^2 (the
 // norm the unitary block receives) when SUM; D_m - 1 goes to dm (registers,
-// for the second half-step), and with DML also to this lane's slots of the
-// LDS array dml (slot E at dml[E W]), from which the second half-step then
-// reads it.  With CACHE, C_m is in `fac` (this lane's slots, no other lane
+// for the second half-step), and with DML also to this lane's entries of the
+// LDS array dml (store_dm4), from which the second half-step then reads it.  With CACHE, C_m is in `fac` (this lane's slots, no other lane
 // reads them) for the second half-step: stored here, or, for a static C
 // (H::kStaticC) when STATIC, already there (fill_static_phase) and read from
 // it instead of the table.
@@ -482,14 +506,16 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
             if constexpr (CACHE) mine[E * W] = C;
         }
         const cx<R> w = u + scale(u, dm[E]);
-        if constexpr (DML) dml[ln.t + E * W] = dm[E];
         if constexpr (SUM) add_abs2(acc, w);
         u = apply_phase(w, C);
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
-        apply(ln.ja + Rr * T, a[Rr], std::integral_constant<int, Rr>{});
-        apply(ln.jb + Rr * T, b[Rr], std::integral_constant<int, R1 + Rr>{});
-        if constexpr ((Rr & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        constexpr int r = Rr;
+        apply(ln.ja + r * T, a[r], std::integral_constant<int, r>{});
+        apply(ln.jb + r * T, b[r], std::integral_constant<int, R1 + r>{});
+        if constexpr (DML && (r & 1) == 1)
+            store_dm4<W>(dml, ln.t, r / 2, dm[r - 1], dm[r], dm[R1 + r - 1], dm[R1 + r]);
+        if constexpr ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     });
     return acc;
 }
@@ -508,6 +534,7 @@ __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
     const cx<R>* mine = fac + ln.t;
     constexpr bool kPairs = !CACHE && H::kPairRows;
     cx<R> pr[kPairs ? 2 * R1 : 1];
+    R dq[4];
     if constexpr (kPairs) load_mirror_pairs<N, W>(h.row, ln, pr);
     auto apply = [&](int m, cx<R>& u, auto E) QT_INL {
         cx<R> C;
@@ -519,15 +546,22 @@ __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
         }
         const cx<R> w = apply_phase(u, C);
         if constexpr (SUM0) add_abs2(x0, w);
-        if constexpr (DML) u = w + scale(w, dml[ln.t + E * W]);
-        else if constexpr (RECOMP) u = w + scale(w, h.damping(m));
-        else u = w + scale(w, dm[E]);
+        if constexpr (DML) {
+            constexpr int e = E;
+            u = w + scale(w, dq[(e < R1 ? 0 : 2) + (e & 1)]);
+        } else if constexpr (RECOMP) {
+            u = w + scale(w, h.damping(m));
+        } else {
+            u = w + scale(w, dm[E]);
+        }
         add_abs2(x1, u);
     };
     sfor<0, R1>([&](auto Rr) QT_INL {
-        apply(ln.ja + Rr * T, a[Rr], std::integral_constant<int, Rr>{});
-        apply(ln.jb + Rr * T, b[Rr], std::integral_constant<int, R1 + Rr>{});
-        if constexpr ((Rr & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        constexpr int r = Rr;
+        if constexpr (DML && (r & 1) == 0) load_dm4<W>(dml, ln.t, r / 2, dq);
+        apply(ln.ja + r * T, a[r], std::integral_constant<int, r>{});
+        apply(ln.jb + r * T, b[r], std::integral_constant<int, R1 + r>{});
+        if constexpr ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     });
 }
 
@@ -769,7 +803,7 @@ void fused_kernel(FusedArgs A)
     constexpr bool kStaticCache = kCache && W > 64;
     __shared__ cx<R> fac[kCache ? N : 1];
     // the lean FP32 form's damping factors between the half-steps
-    __shared__ R dms[FF::kDmLds ? N : 1];
+    __shared__ __attribute__((aligned(16))) R dms[FF::kDmLds ? N : 1];
 
     const Lanes<N, W> ln(threadIdx.x);
     const cx<R>* tw = static_cast<const cx<R>*>(A.tw);
