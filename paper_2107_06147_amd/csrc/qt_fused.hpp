@@ -306,7 +306,11 @@ struct HalfStep {
         else if constexpr (std::is_same<R, double>::value) return expm1_far(zr * x2);
         else return qexpm1(zr * x2);
     }
-    __device__ __forceinline__ cx<R> static_phase(int m) const { return ldg(row, m); }
+    __device__ __forceinline__ cx<R> static_phase(int m) const
+    {
+        static_assert(!kPairRows, "FP32 rows hold mirror pairs: read them with load_mirror_pairs");
+        return ldg(row, m);
+    }
     __device__ __forceinline__ cx<R> phase(cx<R> p, R x2) const
     {
         if constexpr (GAMMA) {
@@ -542,7 +546,8 @@ __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
             C = mine[E * W];
         } else {
             R unused;
-            h.factors(m, kPairs ? pr[E] : h.preload(m), unused, C);
+            if constexpr (kPairs) h.factors(m, pr[E], unused, C);
+            else h.factors(m, h.preload(m), unused, C);
         }
         const cx<R> w = apply_phase(u, C);
         if constexpr (SUM0) add_abs2(x0, w);
