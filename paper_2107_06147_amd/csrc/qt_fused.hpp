@@ -471,10 +471,11 @@ __device__ __forceinline__ void load_dm4(const R* dml, int t, int g, R* d)
 // First half-step: u <- C D u.  Returns this lane's part of sum |D u|^2 (the
 // norm the unitary block receives) when SUM; D_m - 1 goes to dm (registers,
 // for the second half-step), and with DML also to this lane's entries of the
-// LDS array dml (store_dm4), from which the second half-step then reads it.  With CACHE, C_m is in `fac` (this lane's slots, no other lane
-// reads them) for the second half-step: stored here, or, for a static C
-// (H::kStaticC) when STATIC, already there (fill_static_phase) and read from
-// it instead of the table.
+// LDS array dml (store_dm4), from which the second half-step then reads it.
+// With CACHE, C_m is in `fac` (this lane's slots, no other lane reads them)
+// for the second half-step: stored here, or, for a static C (H::kStaticC)
+// when STATIC, already there (fill_static_phase) and read from it instead
+// of the table.
 template <class R, int N, int W, class H, bool CACHE, bool SUM, bool STATIC = false,
           bool DML = false>
 __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
@@ -526,8 +527,8 @@ __device__ __forceinline__ double first_half(cx<R>* a, cx<R>* b, const H& h,
 
 // Second half-step: u <- D C u.  Adds this lane's sum |C u|^2 to x0 (when
 // SUM0) and sum |D C u|^2 to x1.  D_m - 1 comes from dm, with DML from the
-// LDS slots first_half stored it in, with RECOMP from the factor itself
-// (computed again as in first_half, the same value).
+// LDS entries first_half stored it in (load_dm4), with RECOMP from the
+// factor itself (computed again as in first_half, the same value).
 template <class R, int N, int W, class H, bool CACHE, bool SUM0, bool DML = false,
           bool RECOMP = false>
 __device__ __forceinline__ void second_half(cx<R>* a, cx<R>* b, const H& h,
@@ -748,12 +749,13 @@ __device__ __forceinline__ void take_zeroth(const GroupDesc& g, int64_t idx, dou
 // and runs the transforms' lean forms (kin_block32 LEAN, dst1 LATE_KIN).
 // Chosen where the LDS of three waves per SIMD fits in 156 of the CU's 160
 // KiB (a variant at 158 KiB, accepted by the occupancy query, ran 15%
-// slower, as if a workgroup less fitted).  Against the two-wave form with the cache it measured 5% faster
-// without the thermal phase and 9% with it at N = 2048 (FP32, W = 128), 0%
-// and 6% at N = 4096 (FP32, W = 256), 6% and 15% at N = 2048 (FP64,
-// W = 256); and 2% and 5% slower at N = 1024 (FP32) with one wave per
-// workgroup (whose transforms wait at no barrier), which keeps the two-wave
-// form.
+// slower, as if a workgroup less fitted).  Against the two-wave form with
+// the cache it measured 5% faster without the thermal phase and 9% with it
+// at N = 2048 (FP32, W = 128), 0% and 6% at N = 4096 (FP32, W = 256), 6%
+// and 15% at N = 2048 (FP64, W = 256); and 2% and 5% slower at N = 1024
+// (FP32) with one wave per workgroup (whose transforms wait at no barrier),
+// which keeps the two-wave form.  (With the paired table loads, the lead at
+// N = 2048 grew to 22% and 18%.)
 template <class R, int N, int W, int POT>
 struct FusedForm {
     // FP32-bulk renormalises the unitary block of every step
